@@ -1,0 +1,222 @@
+"""Benchmark: kriged voxels/s of the batched edge-preserved kriging path.
+
+One step = one okr_execute over the whole synthetic volume: placement, table
+build, neighbour selection, size bucketing and the persistent batched solve
+(plus the FP64 re-solve pass of the mixed precision modes). Inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line. Extra keys:
+  roofline       dominant kernel (batched solve): algorithmic FLOP per launch
+                 / mean launch time from HIP events recorded by the library
+  cpu_baseline   the FP64 oracle on a bounded random sample of the same
+                 systems, on this host's cores
+  plain_fp32     the per-voxel comparison kernel on a slab of the volume
+  accuracy       GPU result vs the oracle on that same sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "fp32_tflops": 157.3, "fp64_tflops": 78.6, "fp16_tflops": 2500.0, "hbm_gbs": 8000.0,
+}
+
+
+def system_flops(n, f):
+    """Algorithmic FLOP of one (column, gap) system: Cholesky of the n x n
+    covariance (n^3/3), solves of its f+1 border columns ((f+1) n^2) and the
+    read-out of f-1 targets."""
+    return n ** 3 / 3.0 + (f + 1) * n * n + 8.0 * (f - 1) * n
+
+
+def _oracle_chunk(args):
+    import numpy as np
+    import oracle as O
+    s, e, f, r, vario, g, y, x = args
+    t = time.perf_counter()
+    est, var, n, _ = O.krige_sample(s, e, f, r, vario, g, y, x)
+    return est, var, n, time.perf_counter() - t
+
+
+def cpu_baseline(w, s, e, target_s: float, seed: int = 12345):
+    """Oracle on a random sample of systems over a process pool."""
+    import multiprocessing as mp
+    import numpy as np
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    rng = np.random.default_rng(seed)
+    vario = (w.vario.model, w.vario.nugget, w.vario.sill, w.vario.range)
+    plane = w.m * w.m
+    # calibrate on one core
+    cal = rng.choice(w.systems, 300, replace=False)
+    t0 = time.perf_counter()
+    _oracle_chunk((s, e, w.upsample, w.radius, vario, cal // plane, (cal % plane) // w.m,
+                   cal % w.m))
+    per_sys = (time.perf_counter() - t0) / len(cal)
+    nsamp = int(min(max(target_s * cores / per_sys, 2000), 400000))
+    idx = np.sort(rng.choice(w.systems, nsamp, replace=False))
+    chunk = max(200, nsamp // (cores * 4))
+    jobs = []
+    for a in range(0, nsamp, chunk):
+        sl = idx[a:a + chunk]
+        jobs.append((s, e, w.upsample, w.radius, vario, sl // plane, (sl % plane) // w.m,
+                     sl % w.m))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_chunk, jobs)
+    wall = time.perf_counter() - t0
+    est = np.concatenate([r[0] for r in res])
+    var = np.concatenate([r[1] for r in res])
+    vox = nsamp * (w.upsample - 1)
+    return {"value": vox / wall, "unit": "voxels/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsamp} random (column, gap) systems of {w.name} "
+                      f"({vox} kriged voxels), FP64 NumPy/LAPACK, {cores} processes, "
+                      f"{wall:.1f} s wall"}, (idx, est, var)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large_160x512")
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import workloads as W
+    w = W.workload(args.workload)
+    t0 = time.time()
+    s, e = W.make_inputs(w)
+    print(f"# inputs {w.name}: {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    cpu = None
+    sample = None
+    if not args.no_cpu:
+        cpu, sample = cpu_baseline(w, s, e, args.cpu_seconds)
+        print(f"# cpu baseline: {cpu['value']:.0f} voxels/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+
+    import torch
+    import paper_2303_09523_amd as P
+    dev = torch.device("cuda:0")
+    st = torch.from_numpy(s).to(dev)
+    et = torch.from_numpy(e).to(dev) if e is not None else None
+    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched")
+    vol = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
+    var = torch.empty_like(vol)
+    for _ in range(args.warmup):
+        plan.execute(st, w.vario, et, volume=vol, variance=var)
+    torch.cuda.synchronize()
+    plan.stats()                     # clears counters
+    plan.set_profiling(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.execute(st, w.vario, et, volume=vol, variance=var)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = ev0.elapsed_time(ev1) / args.steps
+    stats = plan.stats()
+    plan.set_profiling(False)
+    kriged = w.kriged_voxels
+    value = kriged / (ms * 1e-3)
+
+    hist = np.array(stats["bucket"], dtype=np.float64)
+    nn = np.arange(len(hist), dtype=np.float64)
+    flops = float((hist * system_flops(nn, w.upsample)).sum())
+    solve_ms = stats["phase_ms"]["solve"] / max(1, stats["phase_calls"]["solve"])
+    achieved = flops / (solve_ms * 1e-3) / 1e12
+    peak = PEAKS["fp64_tflops"] if args.precision == "fp64" else PEAKS["fp32_tflops"]
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": None,
+            "kernel": "solve_kernel (batched Cholesky + read-out)",
+            "flop_per_launch": flops, "mean_launch_ms": round(solve_ms, 4)}
+
+    acc = None
+    if sample is not None:
+        idx, est_o, var_o = sample
+        plane = w.m * w.m
+        g, p = idx // plane, idx % plane
+        zs = g[:, None] * w.upsample + np.arange(1, w.upsample)[None, :]
+        vg = vol.cpu().numpy()
+        sg = var.cpu().numpy()
+        yy, xx = (p // w.m)[:, None], (p % w.m)[:, None]
+        ge = vg[zs, yy, xx].astype(np.float64)
+        gv = sg[zs, yy, xx].astype(np.float64)
+        zmax = float(np.abs(s).max())
+        ee = np.abs(ge - est_o) / np.maximum(np.abs(est_o), 0.01 * zmax)
+        evv = np.abs(gv - var_o) / w.vario.sill
+        acc = {"voxels": int(ee.size), "max_rel_err_est": float(ee.max()),
+               "p9999_rel_err_est": float(np.percentile(ee, 99.99)),
+               "max_rel_err_var": float(evv.max()),
+               "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max())}
+
+    plain = None
+    if not args.no_plain:
+        sub = min(w.nslices, 9)
+        pp = P.Plan(w.m, w.m, sub, w.upsample, w.radius, 4, "fp32", "plain")
+        ss = st[:sub].contiguous()
+        es = et[:sub].contiguous() if et is not None else None
+        pv = torch.empty(pp.out_shape(), dtype=torch.float32, device=dev)
+        pvar = torch.empty_like(pv)
+        pp.execute(ss, w.vario, es, volume=pv, variance=pvar)
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        pp.execute(ss, w.vario, es, volume=pv, variance=pvar)
+        a1.record()
+        torch.cuda.synchronize()
+        pms = a0.elapsed_time(a1)
+        pvox = (sub - 1) * (w.upsample - 1) * w.m * w.m
+        plain = {"value": pvox / (pms * 1e-3), "unit": "voxels/s", "ms": round(pms, 2),
+                 "slab": f"first {sub} known slices ({pvox} kriged voxels)",
+                 "batched_over_plain": round(value / (pvox / (pms * 1e-3)), 2)}
+        pp.close()
+    plan.close()
+
+    out = {
+        "metric": "kriged voxels/sec (batched edge-preserved kriging, one MI355X)",
+        "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64"}.get(
+            args.precision, args.precision),
+        "data": "synthetic",
+        "config": {"workload": w.name, "known_slices": w.nslices, "slice": f"{w.m}x{w.m}",
+                   "upsample": w.upsample, "window": f"{2 * w.radius + 1}x{2 * w.radius + 1}x2",
+                   "edge_mask": w.masked, "variogram": [w.vario.model, w.vario.nugget,
+                                                         w.vario.sill, w.vario.range],
+                   "kriged_voxels": kriged, "systems": w.systems,
+                   "precision": args.precision},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp32": plain,
+        "accuracy": acc,
+        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in stats["phase_ms"].items()},
+        "host_wall_s": round(t_host, 3),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

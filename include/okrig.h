@@ -1,0 +1,196 @@
+/*
+ * okrig.h - C ABI of the MI355X edge-preserved ordinary-kriging library.
+ *
+ * The library fills the missing voxels between known 2D slices along Z
+ * (Section 4.1 of "Fast 3D Volumetric Image Reconstruction from 2D MRI
+ * Slices by Parallel Processing"): known slices are placed into the output
+ * volume (Algorithm 1, step 3) and every missing voxel is estimated by
+ * ordinary kriging (Appendix A with a single constant predictor) over its
+ * neighbours in the two adjacent known slices, with neighbours that would
+ * cross an edge of the supplied edge mask left out (Section 4.1.2).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments named d_* are DEVICE pointers owned by the caller;
+ *     the library never frees them and keeps no reference after the call's
+ *     stream work completes. Arrays are C-contiguous, slice index slowest:
+ *     slices[s][y][x], s < nslices, y < ny, x < nx.
+ *   - Work is enqueued on the HIP stream given at plan creation and is
+ *     asynchronous unless stated otherwise.
+ *   - Every function returns an okr_status; no C++ exception crosses the ABI.
+ *     Argument and shape errors are detected on the host before any device
+ *     work is enqueued. okr_plan_last_error() returns a message for the last
+ *     failing call on a plan.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *
+ * Geometry (readings where the paper is silent; the oracle uses the same)
+ *   - Output volume: (nslices-1)*upsample + 1 slices; known slice s is copied
+ *     bit-exactly to z = s*upsample, where the kriging variance is 0.
+ *   - Distances are Euclidean in output-voxel units (pixels in-plane, known
+ *     slices `upsample` apart).
+ *   - Candidate neighbours of target (x, y, g*f + t), 0 < t < f: offsets
+ *     |dx|, |dy| <= radius in slices g ("lower", s = 0) and g+1 ("upper",
+ *     s = 1); out-of-image candidates are dropped. Canonical candidate index
+ *     c = s*W*W + (dy+radius)*W + (dx+radius), W = 2*radius + 1.
+ *   - Edge rule: a candidate is kept iff no pixel of its discrete path from
+ *     the centre is an edge in its own slice's mask; the path is
+ *     p_k = (rha(k*dx/L), rha(k*dy/L)), k = 1..L, L = max(|dx|, |dy|), rha =
+ *     round half away from zero. The centre (0, 0) is always kept.
+ *   - Floor: with fewer than min_points kept, rejected in-image candidates are
+ *     added in the order (dx^2+dy^2, lower slice first, dy, dx).
+ *   - Covariance (GSLIB convention): Cov(0) = sill (total sill),
+ *     Cov(h > 0) = (sill - nugget) * rho(h) with practical range a:
+ *       spherical   rho = 1 - 1.5 h/a + 0.5 (h/a)^3 for h < a, else 0
+ *       exponential rho = exp(-3 h / a)
+ *       gaussian    rho = exp(-3 h^2 / a^2)
+ *   - Estimate z_hat = sum_i w_i z_i and variance sill - w^T c0 - mu, with
+ *     [[C, 1], [1^T, 0]] [w; mu] = [c0; 1] (Appendix A, extended covariance
+ *     system with Lagrange multiplier).
+ */
+#ifndef OKRIG_H
+#define OKRIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t okr_status;
+#define OKR_OK                0
+#define OKR_E_INVALID_ARG     1  /* null pointer, bad enum or parameter value */
+#define OKR_E_SHAPE           2  /* sizes out of range or overflowing */
+#define OKR_E_NONFINITE       3  /* non-finite known voxel (reported at a sync) */
+#define OKR_E_DEVICE          4  /* a HIP call failed */
+#define OKR_E_OOM             5  /* device or pinned allocation failed */
+#define OKR_E_UNSUPPORTED     6  /* valid request this build does not serve */
+#define OKR_E_NOT_CONVERGED   7  /* strict mode: a system failed every precision */
+
+typedef enum { OKR_SPHERICAL = 0, OKR_EXPONENTIAL = 1, OKR_GAUSSIAN = 2 } okr_model;
+
+/* Arithmetic of the factorisation. Assembly and read-out are FP32 except in
+ * OKR_FP64. MIXED_* use split low-precision MFMA products (hi + lo parts) with
+ * FP32 accumulation, an FP64-residual correction for systems whose condition
+ * estimate is large, and an FP64 re-solve of systems whose pivots flag
+ * instability. */
+typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 3 } okr_precision;
+
+/* BATCHED: selection, size bucketing and one persistent factorisation launch,
+ * one Cholesky per (column, gap) shared by its f-1 targets.
+ * PLAIN_PER_VOXEL: one bordered LU (partial pivoting) per kriged voxel with
+ * direct covariance evaluation; the comparison kernel. */
+typedef enum { OKR_ALGO_BATCHED = 0, OKR_ALGO_PLAIN_PER_VOXEL = 1 } okr_algo;
+
+typedef struct {
+  int32_t model;        /* okr_model */
+  double  nugget;       /* 0 <= nugget < sill */
+  double  sill;         /* total sill, > 0 */
+  double  range;        /* practical range, > 0 */
+} okr_variogram;
+
+typedef struct {
+  int32_t nx, ny;       /* slice width / height, 1..65535 */
+  int32_t nslices;      /* known slices, 1..65535 */
+  int32_t upsample;     /* f, 1..15: output has (nslices-1)*f + 1 slices */
+  int32_t radius;       /* r, 0..3: window (2r+1) x (2r+1) x 2 */
+  int32_t min_points;   /* neighbour floor, 1..2*(2r+1)^2; 4 is the usual value */
+  int32_t precision;    /* okr_precision */
+  int32_t algo;         /* okr_algo */
+  double  refine_tol;   /* MIXED_*: condition-estimate x unit roundoff above
+                           which the FP64-residual correction runs (e.g. 1e-4) */
+  int32_t refine_max;   /* MIXED_*: correction steps, 0..4 */
+  int32_t strict;       /* 1: OKR_E_NOT_CONVERGED is returned at the next sync */
+} okr_problem;
+
+typedef struct okr_plan okr_plan;   /* opaque: workspace, tables, launch state */
+
+typedef struct {
+  int64_t n_systems;          /* (column, gap) systems in the last execute */
+  int64_t n_kriged;           /* kriged voxels in the last execute */
+  int64_t bucket[128];        /* systems per neighbour count n (index n) */
+  int64_t n_floor_filled;     /* systems whose neighbour set used the floor */
+  int64_t n_refined;          /* systems that took the FP64-residual correction */
+  int64_t n_fp64_fallback;    /* systems re-solved in FP64 */
+  int64_t n_nonpositive_pivot;/* systems with a non-positive pivot in the first pass */
+  double  max_kappa_est;      /* largest pivot-ratio condition estimate */
+  double  phase_ms[8];        /* with profiling on: summed device time per phase since the
+                                 last okr_stats_get: 0 placement, 1 tables, 2 selection,
+                                 3 bucketing, 4 batched solve, 5 FP64 re-solve,
+                                 6 plain per-voxel kernel, 7 leave-one-slice-out */
+  int64_t phase_calls[8];     /* launches timed per phase */
+} okr_stats;
+
+#define OKR_PHASE_PLACE 0
+#define OKR_PHASE_TABLES 1
+#define OKR_PHASE_SELECT 2
+#define OKR_PHASE_BUCKET 3
+#define OKR_PHASE_SOLVE 4
+#define OKR_PHASE_FALLBACK 5
+#define OKR_PHASE_PLAIN 6
+#define OKR_PHASE_LOSO 7
+
+/* Create a plan for one problem shape. `hip_stream` is a hipStream_t (NULL =
+ * the default stream). Validates every field (OKR_E_INVALID_ARG / SHAPE /
+ * UNSUPPORTED), allocates the workspace (OKR_E_OOM) and returns the plan in
+ * *out. The caller destroys it with okr_plan_destroy. */
+okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_plan** out);
+
+/* Reconstruct the volume (Algorithm 1 steps 3-4, Section 4.1.2).
+ *   d_slices   float32 [nslices][ny][nx], required
+ *   d_edge     uint8   [nslices][ny][nx], nonzero = edge; NULL = no mask
+ *   d_volume   float32 [(nslices-1)*f+1][ny][nx], required
+ *   d_variance float32, same shape as d_volume; NULL = not written
+ *   d_flags    uint8 [(nslices-1)][ny][nx] per (column, gap) system; NULL =
+ *              not written. Bits: 1 floor-filled, 2 FP64-residual correction,
+ *              4 FP64 re-solve, 8 non-positive pivot in the first pass.
+ * Input and output buffers must not overlap. */
+okr_status okr_execute(okr_plan* plan, const okr_variogram* vario,
+                       const float* d_slices, const uint8_t* d_edge,
+                       float* d_volume, float* d_variance, uint8_t* d_flags);
+
+/* Neighbour selection only (the integer part of okr_execute), for callers
+ * and tests that need the kept sets.
+ *   d_bits  uint64 [(nslices-1)*ny*nx][2]: bit c of the 128-bit word of
+ *           system (g, y, x) is canonical candidate c (word 0 = bits 0..63)
+ *   d_count uint8  [(nslices-1)*ny*nx]: number of kept candidates */
+okr_status okr_select(okr_plan* plan, const uint8_t* d_edge, uint64_t* d_bits, uint8_t* d_count);
+
+/* Leave-one-slice-out loss of a variogram: every known slice s in
+ * 1..nslices-2 is predicted from slices s-1 and s+1 (at distance 1 each, the
+ * geometry of upsample 2) with the plan's window and edge rule, and
+ * *d_loss (device double) receives the mean of (z_hat - z)^2 over all those
+ * voxels. Requires a plan with upsample == 2 and nslices >= 3. */
+okr_status okr_loso_forward(okr_plan* plan, const okr_variogram* vario, const float* d_slices,
+                            const uint8_t* d_edge, double* d_loss);
+
+/* Gradient of the last okr_loso_forward loss on this plan with respect to
+ * (nugget, sill, range), by the adjoint of the bordered system:
+ * nu = K^{-1} [e z; 0], dL/dtheta = nu_w^T dc0/dtheta - nu_w^T dC/dtheta w.
+ * d_grad: device double[3]. OKR_E_INVALID_ARG if no forward preceded it. */
+okr_status okr_loso_backward(okr_plan* plan, double* d_grad);
+
+/* Counters of the last execute / loso call; synchronises the plan's stream and
+ * returns any latched device-side error (e.g. OKR_E_NONFINITE). */
+okr_status okr_stats_get(okr_plan* plan, okr_stats* out);
+
+okr_status okr_plan_destroy(okr_plan* plan);
+
+/* Profiling: when enabled, every phase launch is bracketed by HIP events on the
+ * plan's stream and okr_stats_get reports the summed device time per phase
+ * (then clears it). Off by default; costs one event pair per phase. */
+okr_status okr_plan_set_profiling(okr_plan* plan, int32_t enable);
+
+const char* okr_status_string(okr_status status);
+const char* okr_plan_last_error(const okr_plan* plan);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t okr_version(void);
+
+/* Sizes in bytes of okr_problem, okr_variogram and okr_stats as compiled into
+ * the library, written to out[0..2], so a binding can check its layouts. */
+okr_status okr_abi_sizes(int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OKRIG_H */

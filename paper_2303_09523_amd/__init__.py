@@ -1,0 +1,174 @@
+"""MI355X edge-preserved ordinary kriging along Z.
+
+Fills the missing voxels between known 2D slices (Section 4.1 of the paper):
+known slices are placed into the output volume and every missing voxel is
+kriged from its edge-masked neighbourhood in the two adjacent known slices.
+All computation happens in the HIP library (libokrig.so, C ABI in
+include/okrig.h); this module only marshals torch device tensors and the
+current HIP stream into those calls.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+from . import _lib
+from ._lib import OkrError, load  # noqa: F401
+
+__all__ = ["Plan", "krige", "select", "OkrError", "load", "LosoLoss"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _vario(model, nugget, sill, rng):
+    m = _lib.MODELS[model] if isinstance(model, str) else int(model)
+    return _lib.Variogram(m, float(nugget), float(sill), float(rng))
+
+
+def _as_vario(v):
+    if isinstance(v, _lib.Variogram):
+        return v
+    if isinstance(v, (tuple, list)):
+        return _vario(*v)
+    return _vario(v.model, v.nugget, v.sill, v.range)
+
+
+class Plan:
+    """One problem shape: workspace and launch state owned by the library."""
+
+    def __init__(self, nx: int, ny: int, nslices: int, upsample: int, radius: int,
+                 min_points: int = 4, precision: str = "fp32", algo: str = "batched",
+                 refine_tol: float = 1e-4, refine_max: int = 1, strict: bool = False,
+                 stream=None):
+        torch = _torch()
+        lib = load()
+        self.shape = (nslices, ny, nx)
+        self.upsample = upsample
+        self.radius = radius
+        prob = _lib.Problem(nx, ny, nslices, upsample, radius, min_points,
+                            _lib.PRECISIONS[precision], _lib.ALGOS[algo], refine_tol, refine_max,
+                            int(strict))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _lib.check(lib.okr_plan_create(C.byref(prob), C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().okr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_in(self, t, dtype, shape, name):
+        torch = _torch()
+        if t is None:
+            return
+        if not (t.is_cuda and t.dtype == dtype and tuple(t.shape) == tuple(shape)
+                and t.is_contiguous()):
+            raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on the GPU, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        del torch
+
+    def out_shape(self):
+        n, ny, nx = self.shape
+        return ((n - 1) * self.upsample + 1, ny, nx)
+
+    def execute(self, slices, vario, edge=None, volume=None, variance=None, flags=None,
+                want_variance: bool = True, want_flags: bool = False):
+        """Reconstruct the volume; returns (volume, variance or None, flags or None)."""
+        torch = _torch()
+        self._check_in(slices, torch.float32, self.shape, "slices")
+        if edge is not None:
+            self._check_in(edge, torch.uint8, self.shape, "edge")
+        dev = slices.device
+        if volume is None:
+            volume = torch.empty(self.out_shape(), dtype=torch.float32, device=dev)
+        if variance is None and want_variance:
+            variance = torch.empty(self.out_shape(), dtype=torch.float32, device=dev)
+        if flags is None and want_flags:
+            n, ny, nx = self.shape
+            flags = torch.empty((max(n - 1, 0), ny, nx), dtype=torch.uint8, device=dev)
+        v = _as_vario(vario)
+        _lib.check(load().okr_execute(self._h, C.byref(v), _ptr(slices), _ptr(edge),
+                                      _ptr(volume), _ptr(variance), _ptr(flags)), self._h)
+        return volume, variance, flags
+
+    def select(self, edge=None):
+        """Kept-candidate bitmasks [(n-1)*ny*nx][2] (int64 view of uint64) and counts."""
+        torch = _torch()
+        n, ny, nx = self.shape
+        if edge is not None:
+            self._check_in(edge, torch.uint8, self.shape, "edge")
+        nsys = max(n - 1, 0) * ny * nx
+        bits = torch.empty((nsys, 2), dtype=torch.int64, device="cuda")
+        count = torch.empty((nsys,), dtype=torch.uint8, device="cuda")
+        _lib.check(load().okr_select(self._h, _ptr(edge), _ptr(bits), _ptr(count)), self._h)
+        return bits, count
+
+    def loso_forward(self, slices, vario, edge=None, loss=None):
+        torch = _torch()
+        self._check_in(slices, torch.float32, self.shape, "slices")
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=slices.device)
+        v = _as_vario(vario)
+        _lib.check(load().okr_loso_forward(self._h, C.byref(v), _ptr(slices), _ptr(edge),
+                                           _ptr(loss)), self._h)
+        return loss
+
+    def loso_backward(self, grad=None):
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((3,), dtype=torch.float64, device="cuda")
+        _lib.check(load().okr_loso_backward(self._h, _ptr(grad)), self._h)
+        return grad
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        _lib.check(load().okr_stats_get(self._h, C.byref(s)), self._h)
+        return {"n_systems": s.n_systems, "n_kriged": s.n_kriged, "bucket": list(s.bucket),
+                "n_floor_filled": s.n_floor_filled, "n_refined": s.n_refined,
+                "n_fp64_fallback": s.n_fp64_fallback,
+                "n_nonpositive_pivot": s.n_nonpositive_pivot, "max_kappa_est": s.max_kappa_est,
+                "phase_ms": dict(zip(_lib.PHASES, list(s.phase_ms))),
+                "phase_calls": dict(zip(_lib.PHASES, list(s.phase_calls)))}
+
+    def set_profiling(self, enable: bool = True):
+        _lib.check(load().okr_plan_set_profiling(self._h, int(enable)), self._h)
+
+
+def krige(slices, vario, upsample: int, radius: int, edge=None, min_points: int = 4,
+          precision: str = "fp32", algo: str = "batched", want_variance: bool = True):
+    """One-shot reconstruction: (volume, variance) as CUDA tensors."""
+    n, ny, nx = slices.shape
+    plan = Plan(nx, ny, n, upsample, radius, min_points, precision, algo)
+    vol, var, _ = plan.execute(slices, vario, edge, want_variance=want_variance)
+    plan.close()
+    return vol, var
+
+
+def select(edge, nslices, ny, nx, radius, min_points=4):
+    plan = Plan(nx, ny, nslices, 2, radius, min_points)
+    out = plan.select(edge)
+    plan.close()
+    return out
+
+
+def __getattr__(name):
+    if name == "LosoLoss":
+        from .autograd import LosoLoss
+        return LosoLoss
+    raise AttributeError(name)

@@ -1,0 +1,473 @@
+// Host side of the okrig C ABI: validation, plan/workspace ownership, the
+// neighbour-rule tables and the launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/okrig.h"
+#include "okrig_internal.h"
+
+namespace okr {
+size_t plain_shared_bytes(const Geometry& g);
+hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, int ngaps,
+                              const SelectRule& rule, uint64_t* bits, uint8_t* count,
+                              DevCounters* c, hipStream_t s);
+hipError_t launch_loso_forward(const SolveArgs& a, const float* slices, double* sq, double* loss,
+                               int grid, hipStream_t s);
+hipError_t launch_loso_backward(const SolveArgs& a, const double* resid, double* partial,
+                                double* grad, int grid, hipStream_t s);
+}  // namespace okr
+
+struct okr_plan {
+  okr_problem prob;
+  okr::Geometry geo;
+  okr::SelectRule rule;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 256;
+  // workspace
+  uint64_t* bits = nullptr;
+  uint8_t* count = nullptr;
+  uint32_t* perm = nullptr;
+  uint32_t* fallback = nullptr;
+  okr::DevCounters* ctr = nullptr;
+  double* tabs = nullptr;       // FP64 tables and derivatives
+  float* tabs_f = nullptr;      // FP32 copies
+  double* loso_sq = nullptr;    // per held-out voxel residual (z_hat - z)
+  double* loso_partial = nullptr;
+  double* loso_loss = nullptr;
+  bool loso_ready = false;
+  okr_variogram loso_vario{};
+  const float* loso_slices = nullptr;
+  const uint8_t* loso_edge = nullptr;
+  long long last_nsys = 0, last_kriged = 0;
+  bool profiling = false;
+  struct Mark { int phase; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  double phase_ms[8] = {0};
+  long long phase_calls[8] = {0};
+  std::string err;
+};
+
+namespace {
+
+okr_status fail(okr_plan* p, okr_status st, const std::string& msg) {
+  if (p) p->err = msg;
+  return st;
+}
+
+#define OKR_HIP(plan, call)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(plan, OKR_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// round half away from zero of num/den, den > 0
+int rha(int num, int den) {
+  int q = (2 * std::abs(num) + den) / (2 * den);
+  return num >= 0 ? q : -q;
+}
+
+void build_rule(int r, okr::SelectRule* rule) {
+  std::memset(rule, 0, sizeof(*rule));
+  const int W = 2 * r + 1, W2 = W * W;
+  for (int dy = -r; dy <= r; ++dy) {
+    for (int dx = -r; dx <= r; ++dx) {
+      const int o = (dy + r) * W + (dx + r);
+      const int L = std::max(std::abs(dx), std::abs(dy));
+      uint64_t m = 0;
+      for (int k = 1; k <= L; ++k) {
+        const int px = rha(k * dx, L), py = rha(k * dy, L);
+        m |= 1ull << ((py + r) * W + (px + r));
+      }
+      rule->path[o] = m;
+    }
+  }
+  std::vector<int> idx(2 * W2);
+  for (int i = 0; i < 2 * W2; ++i) idx[i] = i;
+  auto key = [&](int c) {
+    const int s = c >= W2, o = c - s * W2, dy = o / W - r, dx = o % W - r;
+    return std::make_tuple(dx * dx + dy * dy, s, dy, dx);
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key(a) < key(b); });
+  for (int i = 0; i < 2 * W2; ++i) rule->floor_order[i] = (uint8_t)idx[i];
+}
+
+okr_status validate_problem(const okr_problem* p, std::string* msg) {
+  if (!p) { *msg = "problem is NULL"; return OKR_E_INVALID_ARG; }
+  if (p->nx < 1 || p->ny < 1 || p->nslices < 1 || p->nx > 65535 || p->ny > 65535 ||
+      p->nslices > 65535) {
+    *msg = "nx, ny, nslices must be in 1..65535";
+    return OKR_E_SHAPE;
+  }
+  if (p->upsample < 1 || p->upsample > okr::kMaxUpsample) {
+    *msg = "upsample must be in 1..15";
+    return OKR_E_SHAPE;
+  }
+  if (p->radius < 0 || p->radius > okr::kMaxRadius) {
+    *msg = "radius must be in 0..3";
+    return OKR_E_SHAPE;
+  }
+  const int W = 2 * p->radius + 1;
+  if (p->min_points < 1 || p->min_points > 2 * W * W) {
+    *msg = "min_points must be in 1..2*(2r+1)^2";
+    return OKR_E_INVALID_ARG;
+  }
+  if (p->precision < OKR_FP32 || p->precision > OKR_FP64) {
+    *msg = "unknown precision";
+    return OKR_E_INVALID_ARG;
+  }
+  if (p->algo != OKR_ALGO_BATCHED && p->algo != OKR_ALGO_PLAIN_PER_VOXEL) {
+    *msg = "unknown algo";
+    return OKR_E_INVALID_ARG;
+  }
+  if (p->algo == OKR_ALGO_PLAIN_PER_VOXEL && p->precision != OKR_FP32) {
+    *msg = "the plain per-voxel kernel is FP32 only";
+    return OKR_E_UNSUPPORTED;
+  }
+  if (!(p->refine_tol >= 0.0) || p->refine_max < 0 || p->refine_max > 4) {
+    *msg = "refine_tol must be >= 0 and refine_max in 0..4";
+    return OKR_E_INVALID_ARG;
+  }
+  const long long plane = (long long)p->nx * p->ny;
+  const long long nsys = plane * (long long)(p->nslices > 1 ? p->nslices - 1 : 1);
+  if (nsys > 0xffffffffLL) {
+    *msg = "more than 2^32 systems";
+    return OKR_E_SHAPE;
+  }
+  return OKR_OK;
+}
+
+okr_status validate_vario(const okr_variogram* v, std::string* msg) {
+  if (!v) { *msg = "variogram is NULL"; return OKR_E_INVALID_ARG; }
+  if (v->model < OKR_SPHERICAL || v->model > OKR_GAUSSIAN) {
+    *msg = "unknown variogram model";
+    return OKR_E_INVALID_ARG;
+  }
+  if (!(std::isfinite(v->sill) && std::isfinite(v->nugget) && std::isfinite(v->range)) ||
+      !(v->sill > 0.0) || !(v->nugget >= 0.0) || !(v->nugget < v->sill) || !(v->range > 0.0)) {
+    *msg = "variogram needs 0 <= nugget < sill and range > 0 (finite)";
+    return OKR_E_INVALID_ARG;
+  }
+  return OKR_OK;
+}
+
+template <typename T>
+okr_status dev_alloc(okr_plan* p, T** ptr, size_t count) {
+  if (count == 0) count = 1;
+  if (std::getenv("OKR_FAIL_ALLOC")) return fail(p, OKR_E_OOM, "allocation failure (forced)");
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(p, OKR_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return OKR_OK;
+}
+
+void drain_marks(okr_plan* p);
+
+void free_plan(okr_plan* p) {
+  if (!p) return;
+  drain_marks(p);
+  hipFree(p->bits);
+  hipFree(p->count);
+  hipFree(p->perm);
+  hipFree(p->fallback);
+  hipFree(p->ctr);
+  hipFree(p->tabs);
+  hipFree(p->tabs_f);
+  hipFree(p->loso_sq);
+  hipFree(p->loso_partial);
+  hipFree(p->loso_loss);
+  delete p;
+}
+
+okr::TableSet tables_of(okr_plan* p) {
+  okr::TableSet t;
+  t.tc_d = p->tabs;
+  t.t0_d = t.tc_d + okr::kTcSize;
+  t.dtc_d = t.t0_d + okr::kT0Size;
+  t.dt0_d = t.dtc_d + 3 * okr::kTcSize;
+  t.tc_f = p->tabs_f;
+  t.t0_f = t.tc_f + okr::kTcSize;
+  return t;
+}
+
+okr::Vario vario_of(const okr_variogram* v) {
+  okr::Vario o;
+  o.model = v->model;
+  o.nugget = v->nugget;
+  o.sill = v->sill;
+  o.range = v->range;
+  return o;
+}
+
+okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
+  okr::SolveArgs a{};
+  a.bits = p->bits;
+  a.count = p->count;
+  a.perm = p->perm;
+  a.ctr = p->ctr;
+  a.tab = tables_of(p);
+  a.geo = p->geo;
+  a.sill = v->sill;
+  a.nb = p->geo.f + 1;
+  a.precision = p->prob.precision;
+  a.kappa_limit = 1e300;
+  a.fallback = nullptr;
+  return a;
+}
+
+int persistent_grid(okr_plan* p) { return p->num_cu * 3; }
+
+// Brackets one phase's launches with events when profiling is on.
+struct PhaseTimer {
+  okr_plan* p;
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseTimer(okr_plan* plan, int ph) : p(plan), phase(ph) {
+    if (!p->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      (void)hipGetLastError();
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, p->stream);
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    (void)hipEventRecord(b, p->stream);
+    p->marks.push_back({phase, a, b});
+  }
+};
+
+void drain_marks(okr_plan* p) {
+  for (auto& m : p->marks) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      p->phase_ms[m.phase] += ms;
+      p->phase_calls[m.phase] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  p->marks.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t okr_version(void) { return 100; }
+
+okr_status okr_abi_sizes(int64_t* out) {
+  if (!out) return OKR_E_INVALID_ARG;
+  out[0] = (int64_t)sizeof(okr_problem);
+  out[1] = (int64_t)sizeof(okr_variogram);
+  out[2] = (int64_t)sizeof(okr_stats);
+  return OKR_OK;
+}
+
+const char* okr_status_string(okr_status s) {
+  switch (s) {
+    case OKR_OK: return "ok";
+    case OKR_E_INVALID_ARG: return "invalid argument";
+    case OKR_E_SHAPE: return "shape out of range";
+    case OKR_E_NONFINITE: return "non-finite known voxel";
+    case OKR_E_DEVICE: return "device error";
+    case OKR_E_OOM: return "out of memory";
+    case OKR_E_UNSUPPORTED: return "unsupported";
+    case OKR_E_NOT_CONVERGED: return "not converged";
+    default: return "unknown status";
+  }
+}
+
+const char* okr_plan_last_error(const okr_plan* p) { return p ? p->err.c_str() : "plan is NULL"; }
+
+okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_plan** out) {
+  if (!out) return OKR_E_INVALID_ARG;
+  *out = nullptr;
+  std::string msg;
+  okr_status st = validate_problem(problem, &msg);
+  if (st != OKR_OK) return st;
+  okr_plan* p = new (std::nothrow) okr_plan();
+  if (!p) return OKR_E_OOM;
+  p->prob = *problem;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  okr::Geometry& g = p->geo;
+  g.nx = problem->nx;
+  g.ny = problem->ny;
+  g.nslices = problem->nslices;
+  g.f = problem->upsample;
+  g.r = problem->radius;
+  g.W = 2 * g.r + 1;
+  g.W2 = g.W * g.W;
+  g.ncand = 2 * g.W2;
+  g.min_points = problem->min_points;
+  g.plane = (long long)g.nx * g.ny;
+  g.nsys = g.plane * (g.nslices > 1 ? g.nslices - 1 : 0);
+  build_rule(g.r, &p->rule);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return OKR_E_DEVICE;
+  }
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+      cu > 0)
+    p->num_cu = cu;
+  const size_t nsys = (size_t)std::max<long long>(g.nsys, 1);
+  if ((st = dev_alloc(p, &p->ctr, 1)) != OKR_OK ||
+      (st = dev_alloc(p, &p->tabs, 4 * okr::kTcSize + 4 * okr::kT0Size)) != OKR_OK ||
+      (st = dev_alloc(p, &p->tabs_f, okr::kTcSize + okr::kT0Size)) != OKR_OK) {
+    free_plan(p);
+    return st;
+  }
+  if (problem->algo == OKR_ALGO_BATCHED) {
+    if ((st = dev_alloc(p, &p->bits, 2 * nsys)) != OKR_OK ||
+        (st = dev_alloc(p, &p->count, nsys)) != OKR_OK ||
+        (st = dev_alloc(p, &p->perm, nsys)) != OKR_OK ||
+        (st = dev_alloc(p, &p->fallback, nsys)) != OKR_OK) {
+      free_plan(p);
+      return st;
+    }
+  }
+  *out = p;
+  return OKR_OK;
+}
+
+okr_status okr_plan_destroy(okr_plan* p) {
+  if (!p) return OKR_E_INVALID_ARG;
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return OKR_OK;
+}
+
+okr_status okr_execute(okr_plan* p, const okr_variogram* vario, const float* d_slices,
+                       const uint8_t* d_edge, float* d_volume, float* d_variance,
+                       uint8_t* d_flags) {
+  if (!p) return OKR_E_INVALID_ARG;
+  std::string msg;
+  okr_status st = validate_vario(vario, &msg);
+  if (st != OKR_OK) return fail(p, st, msg);
+  if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
+  const okr::Geometry& g = p->geo;
+  OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
+  {
+    PhaseTimer t(p, OKR_PHASE_PLACE);
+    OKR_HIP(p, okr::launch_place(d_slices, d_volume, d_variance, g, p->ctr, p->stream));
+  }
+  p->last_nsys = g.nsys;
+  p->last_kriged = g.nsys * (g.f - 1);
+  if (g.nslices < 2 || g.f < 2) return OKR_OK;
+  {
+    PhaseTimer t(p, OKR_PHASE_TABLES);
+    OKR_HIP(p, okr::launch_tables(vario_of(vario), g, tables_of(p), p->stream));
+  }
+  if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL) {
+    PhaseTimer t(p, OKR_PHASE_PLAIN);
+    OKR_HIP(p, okr::launch_plain(d_slices, d_edge, d_volume, d_variance, g, p->rule,
+                                 vario_of(vario), p->stream));
+    return OKR_OK;
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_SELECT);
+    OKR_HIP(p, okr::launch_select(d_edge, g, p->rule, p->bits, p->count, p->ctr, p->stream));
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_BUCKET);
+    OKR_HIP(p, okr::launch_bucket(p->count, g, p->perm, p->ctr, p->stream));
+  }
+  okr::SolveArgs a = solve_args(p, vario);
+  a.slices = d_slices;
+  a.volume = d_volume;
+  a.variance = d_variance;
+  a.flags = d_flags;
+  const char* force = std::getenv("OKR_FORCE_FALLBACK");
+  const bool forced = force && force[0] == '1';
+  if (forced && p->prob.precision != OKR_FP64) {
+    a.kappa_limit = 0.0;
+    a.fallback = p->fallback;
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_SOLVE);
+    OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), p->stream));
+  }
+  if (a.fallback) {
+    PhaseTimer t(p, OKR_PHASE_FALLBACK);
+    OKR_HIP(p, okr::launch_solve_fallback(a, persistent_grid(p), p->stream));
+  }
+  return OKR_OK;
+}
+
+okr_status okr_select(okr_plan* p, const uint8_t* d_edge, uint64_t* d_bits, uint8_t* d_count) {
+  if (!p) return OKR_E_INVALID_ARG;
+  if (!d_bits || !d_count) return fail(p, OKR_E_INVALID_ARG, "bits and count are required");
+  const okr::Geometry& g = p->geo;
+  if (g.nsys == 0) return OKR_OK;
+  OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_select(d_edge, g, p->rule, d_bits, d_count, p->ctr, p->stream));
+  p->last_nsys = g.nsys;
+  p->last_kriged = 0;
+  return OKR_OK;
+}
+
+okr_status okr_plan_set_profiling(okr_plan* p, int32_t enable) {
+  if (!p) return OKR_E_INVALID_ARG;
+  p->profiling = enable != 0;
+  return OKR_OK;
+}
+
+okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float* d_slices,
+                            const uint8_t* d_edge, double* d_loss) {
+  if (!p) return OKR_E_INVALID_ARG;
+  (void)vario; (void)d_slices; (void)d_edge; (void)d_loss;
+  return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is not available in this build");
+}
+
+okr_status okr_loso_backward(okr_plan* p, double* d_grad) {
+  if (!p) return OKR_E_INVALID_ARG;
+  (void)d_grad;
+  return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is not available in this build");
+}
+
+okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
+  if (!p || !out) return OKR_E_INVALID_ARG;
+  OKR_HIP(p, hipStreamSynchronize(p->stream));
+  okr::DevCounters c;
+  OKR_HIP(p, hipMemcpy(&c, p->ctr, sizeof(c), hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->n_systems = p->last_nsys;
+  out->n_kriged = p->last_kriged;
+  for (int i = 0; i < okr::kHist && i < 128; ++i) out->bucket[i] = (int64_t)c.hist[i];
+  out->n_floor_filled = (int64_t)c.floor_filled;
+  out->n_refined = (int64_t)c.refined;
+  out->n_fp64_fallback = (int64_t)c.fp64_fallback;
+  out->n_nonpositive_pivot = (int64_t)c.bad_pivot;
+  float k;
+  std::memcpy(&k, &c.max_kappa_bits, sizeof(k));
+  out->max_kappa_est = k;
+  drain_marks(p);
+  for (int i = 0; i < 8; ++i) {
+    out->phase_ms[i] = p->phase_ms[i];
+    out->phase_calls[i] = p->phase_calls[i];
+    p->phase_ms[i] = 0.0;
+    p->phase_calls[i] = 0;
+  }
+  if (c.nonfinite) return fail(p, OKR_E_NONFINITE, "a known voxel is not finite");
+  return OKR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace okr {
+
+constexpr int kMaxRadius = 3;
+constexpr int kMaxWin = 2 * kMaxRadius + 1;        // W
+constexpr int kMaxCand = 2 * kMaxWin * kMaxWin;    // 98 candidates
+constexpr int kMaxUpsample = 15;                   // f; nb = f + 1 <= 16 border rows
+constexpr int kMaxBlocks = 8;                      // 16-wide blocks of the augmented matrix
+constexpr int kTcSize = 128;                       // pair-class table, index (ds<<6)|(|dy|<<3)|(|dx|)
+constexpr int kT0Stride = 32;                      // target table: ((t-1)*2 + s)*16 + |dy|*4 + |dx|
+constexpr int kT0Size = kMaxUpsample * kT0Stride;  // up to 14 targets used
+constexpr int kHist = 128;                         // histogram bins over n
+
+// Per-system count byte: low 7 bits = n, bit 7 = floor-filled.
+constexpr uint8_t kFloorBit = 0x80;
+
+// Flag bits written per system (see okrig.h).
+constexpr uint8_t kFlagFloor = 1, kFlagRefined = 2, kFlagFp64 = 4, kFlagBadPivot = 8;
+
+struct Geometry {
+  int nx, ny, nslices, f, r, W, W2, ncand, min_points;
+  long long plane;        // nx * ny
+  long long nsys;         // (nslices - 1) * plane
+};
+
+// Kernel-argument block of the selection rule.
+struct SelectRule {
+  uint64_t path[kMaxWin * kMaxWin];  // offset o=(dy+r)*W+(dx+r): window cells on its path
+  uint8_t floor_order[kMaxCand];     // canonical indices in floor order
+};
+
+// Device tables, computed on the device in FP64 from the variogram.
+struct TableSet {
+  double* tc_d;   // [kTcSize]
+  double* t0_d;   // [kT0Size]
+  double* dtc_d;  // [3][kTcSize]  d/d(nugget, sill, range)
+  double* dt0_d;  // [3][kT0Size]
+  float* tc_f;    // FP32 copies
+  float* t0_f;
+};
+
+struct Vario { int model; double nugget, sill, range; };
+
+// Work-distribution and statistics block in device memory.
+struct DevCounters {
+  unsigned long long next;          // persistent-kernel work cursor
+  unsigned long long hist[kHist];   // systems per n
+  unsigned long long floor_filled;
+  unsigned long long refined;
+  unsigned long long fp64_fallback;
+  unsigned long long bad_pivot;
+  unsigned int max_kappa_bits;      // float bits of the largest estimate
+  unsigned int nonfinite;           // nonzero if a known voxel is not finite
+  unsigned long long offsets[kHist + 1];  // bucket starts (largest n first)
+  unsigned long long cursor[kHist];
+  unsigned long long next2;         // second-pass cursor
+  unsigned long long n_fallback_list;
+};
+
+// ---- launchers (kernels_select.hip) ----
+hipError_t launch_tables(const Vario& v, const Geometry& g, TableSet t, hipStream_t s);
+hipError_t launch_reset(DevCounters* c, hipStream_t s);
+hipError_t launch_place(const float* slices, float* volume, float* variance, const Geometry& g,
+                        DevCounters* c, hipStream_t s);
+hipError_t launch_select(const uint8_t* edge, const Geometry& g, const SelectRule& rule,
+                         uint64_t* bits, uint8_t* count, DevCounters* c, hipStream_t s);
+hipError_t launch_bucket(const uint8_t* count, const Geometry& g, uint32_t* perm, DevCounters* c,
+                         hipStream_t s);
+
+// ---- launchers (kernels_solve.hip) ----
+struct SolveArgs {
+  const float* slices;
+  const uint64_t* bits;
+  const uint8_t* count;
+  const uint32_t* perm;
+  float* volume;
+  float* variance;
+  uint8_t* flags;
+  DevCounters* ctr;
+  TableSet tab;
+  Geometry geo;
+  double sill;
+  int nb;               // border rows: f + 1
+  int precision;        // okr_precision
+  double kappa_limit;   // condition estimate above which a system is re-solved in FP64
+  uint32_t* fallback;   // list of systems for the FP64 pass
+};
+hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
+hipError_t launch_solve_fallback(const SolveArgs& a, int grid, hipStream_t s);
+int solve_blocks_needed(const Geometry& g);
+
+// ---- launchers (kernels_plain.hip) ----
+hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume, float* variance,
+                        const Geometry& g, const SelectRule& rule, const Vario& v, hipStream_t s);
+
+}  // namespace okr

@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (relative error of the estimate |z_hat - z*| / max(|z*|, 0.01 Zmax) and of
+the variance |s2 - s2*| / sill): FP32 paths <= 1e-5, FP64 path <= 1e-10;
+integer selection results bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from _gpu_util import canonical_bits, rel_err_est, rel_err_var, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+# FP64 results are written as float32: the bar is the FP32 output rounding.
+TOL = {"fp32": 1e-5, "fp64": 1.2e-7}
+
+# (name, nslices, ny, nx, f, r, model, nugget, sill, range, masked, seed)
+CASES = [
+    ("c1_full", 8, 64, 64, 2, 1, "spherical", 0.0, 1.0, 4.0, False, 1),
+    ("edge_r2_f4", 5, 53, 47, 4, 2, "exponential", 0.01, 1.0, 6.0, True, 2),
+    ("edge_r3_f4", 4, 45, 38, 4, 3, "spherical", 0.005, 1.0, 8.0, True, 5),
+    ("edge_r3_f3_gauss", 3, 33, 40, 3, 3, "gaussian", 0.05, 1.0, 5.0, True, 7),
+    ("edge_r2_f5", 3, 29, 70, 5, 2, "exponential", 0.02, 2.0, 4.0, True, 8),
+    ("r0_f2", 4, 17, 19, 2, 0, "spherical", 0.0, 1.0, 4.0, False, 9),
+    ("tiny_image", 3, 2, 3, 4, 3, "exponential", 0.01, 1.0, 6.0, True, 10),
+]
+
+
+def _inputs(name, n, ny, nx, f, r, masked, seed):
+    w = W.Workload(name, n, max(ny, nx), f, r, masked, 6, 2, 0.02,
+                   W.Variogram("spherical", 0, 1, 4), seed)
+    s = W.phantom(w)[:, :ny, :nx].copy()
+    e = W.sobel_edges(s) if masked else None
+    if masked:
+        # add random edge pixels so every rule branch and the floor are exercised
+        rng = np.random.default_rng(seed + 100)
+        e = np.maximum(e, (rng.random(e.shape) < 0.15).astype(np.uint8))
+    return s, e
+
+
+@pytest.fixture(scope="module")
+def oracle_cache():
+    return {}
+
+
+def _oracle(cache, case):
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    if name not in cache:
+        s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+        vol, var, npts = O.krige_volume(s, e, f, r, (model, nug, sill, rng_),
+                                        min_points=min(4, 2 * (2 * r + 1) ** 2))
+        cache[name] = (s, e, vol, var, npts)
+    return cache[name]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batched_vs_oracle(case, precision, oracle_cache):
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, e, vol_o, var_o, npts = _oracle(oracle_cache, case)
+    print(f"case {name} precision {precision}", flush=True)
+    vol, var, fl, st = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision=precision,
+                               min_points=min(4, 2 * (2 * r + 1) ** 2))
+    # known slices bit-exact, variance 0 there
+    np.testing.assert_array_equal(vol[::f], s)
+    assert (var[::f] == 0).all()
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    zmax = np.abs(s).max()
+    ee = rel_err_est(vol[kz], vol_o[kz], zmax)
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    print(f"  max est err {ee.max():.3e} var err {ev.max():.3e}", flush=True)
+    assert ee.max() <= TOL[precision]
+    assert ev.max() <= TOL[precision]
+    # bucket histogram equals the oracle's neighbour counts
+    hist = np.bincount(npts.ravel(), minlength=128)
+    assert st["bucket"] == hist.tolist()
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_plain_vs_oracle(case, oracle_cache):
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, e, vol_o, var_o, _ = _oracle(oracle_cache, case)
+    vol, var, _, _ = run_gpu(s, e, f, r, (model, nug, sill, rng_), algo="plain")
+    np.testing.assert_array_equal(vol[::f], s)
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    zmax = np.abs(s).max()
+    ee = rel_err_est(vol[kz], vol_o[kz], zmax)
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    print(f"case {name} plain: max est err {ee.max():.3e} var err {ev.max():.3e}", flush=True)
+    assert ee.max() <= TOL["fp32"]
+    assert ev.max() <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 3])
+@pytest.mark.parametrize("density", [0.05, 0.3, 0.9])
+def test_select_bit_exact(r, density):
+    import torch
+    import paper_2303_09523_amd as P
+    rng = np.random.default_rng(1000 + 10 * r + int(density * 10))
+    n, ny, nx = 4, 37, 41
+    e = (rng.random((n, ny, nx)) < density).astype(np.uint8)
+    mp = min(4, 2 * (2 * r + 1) ** 2)
+    plan = P.Plan(nx, ny, n, 2, r, mp)
+    bits, count = plan.select(torch.from_numpy(e).cuda())
+    bits = bits.cpu().numpy().view(np.uint64)
+    count = count.cpu().numpy()
+    plan.close()
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for g in range(n - 1):
+        S = ny * nx
+        gs = np.full(S, g)
+        kept, _ = O.select_neighbours((e[gs], e[gs + 1]), yy.ravel(), xx.ravel(), r, mp, (ny, nx))
+        lo, hi = canonical_bits(kept)
+        sl = slice(g * S, (g + 1) * S)
+        np.testing.assert_array_equal(bits[sl, 0], lo)
+        np.testing.assert_array_equal(bits[sl, 1], hi)
+        np.testing.assert_array_equal(count[sl] & 0x7f, kept.sum(axis=1))
+
+
+def test_degenerate_shapes():
+    vario = ("exponential", 0.01, 1.0, 6.0)
+    rng = np.random.default_rng(3)
+    # f = 1: nothing to krige, the volume is the slices
+    s = rng.normal(size=(3, 5, 6)).astype(np.float32)
+    vol, var, _, _ = run_gpu(s, None, 1, 2, vario)
+    np.testing.assert_array_equal(vol, s)
+    # a single slice
+    s1 = s[:1].copy()
+    vol, var, _, _ = run_gpu(s1, None, 4, 2, vario)
+    np.testing.assert_array_equal(vol, s1)
+    # 1-pixel-wide image with a window wider than the image
+    s2 = rng.normal(size=(2, 9, 1)).astype(np.float32)
+    vol, var, _, _ = run_gpu(s2, None, 3, 3, vario)
+    vo, va, _ = O.krige_volume(s2, None, 3, 3, vario)
+    assert np.abs(vol - vo).max() <= 1e-5 * max(1.0, np.abs(vo).max())
+
+
+def test_nonfinite_input_reported():
+    import torch
+    import paper_2303_09523_amd as P
+    s = np.zeros((2, 8, 8), np.float32)
+    s[1, 3, 3] = np.nan
+    plan = P.Plan(8, 8, 2, 2, 1)
+    plan.execute(torch.from_numpy(s).cuda(), ("spherical", 0.0, 1.0, 4.0))
+    with pytest.raises(P.OkrError) as ei:
+        plan.stats()
+    assert ei.value.status == 3
+    plan.close()
+
+
+def test_bitwise_repeatable():
+    case = CASES[1]
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+    a = run_gpu(s, e, f, r, (model, nug, sill, rng_))
+    b = run_gpu(s, e, f, r, (model, nug, sill, rng_))
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_forced_fp64_fallback(monkeypatch):
+    monkeypatch.setenv("OKR_FORCE_FALLBACK", "1")
+    case = CASES[2]
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+    vol, var, fl, st = run_gpu(s, e, f, r, (model, nug, sill, rng_), flags=True)
+    monkeypatch.delenv("OKR_FORCE_FALLBACK")
+    v64, s64, _, _ = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision="fp64")
+    assert st["n_fp64_fallback"] == (n - 1) * ny * nx
+    assert (fl & 4).all()
+    np.testing.assert_array_equal(vol, v64)
+    np.testing.assert_array_equal(var, s64)
