@@ -1,0 +1,104 @@
+// Mixed-precision batched kriging with an FP64 residual correction.
+//
+// Per system (one wavefront):
+//   1. The data values are shifted by a reference value z_ref (the first kept
+//      point) and divided by a power of two s that bounds their spread, and the
+//      covariances are divided by the sill. Ordinary kriging is affine in the
+//      data and invariant to a common scale of C and c0, so
+//      z_hat = z_ref + s * z_hat' and sigma^2 = sill * sigma'^2, while every
+//      low-precision operand stays O(1).
+//   2. Left-looking factorisation of [[C, B], [B^T, 0]] with FP32 diagonal
+//      tiles and off-diagonal solves and split FP16 (or BF16) MFMA trailing
+//      updates (hi*hi + hi*lo + lo*hi, FP32 accumulation).
+//   3. Back-substitution gives x_1 = C^{-1} 1, x_z = C^{-1} z, x_t = C^{-1} c0_t,
+//      hence the weights w_t = x_t - mu_t x_1 (mu_t = (1'x_t - 1) / 1'x_1) and
+//      the adjoint vector nu_w = x_z - (1'x_z / 1'x_1) x_1 with
+//      nu_mu = 1'x_z / 1'x_1 of the bordered system K = [[C, 1], [1', 0]].
+//   4. FP64 correction with the residual r_t - K lambda_t of the FP64 system:
+//        z_hat_t = z' w_t + nu' r_t - (K nu)' lambda_t
+//      which is exact up to the product of the errors of nu and lambda_t, so
+//      the estimate reaches FP64-level accuracy from a low-precision factor.
+//      The one FP64 matrix-vector product C nu_w per system uses the FP64
+//      pair-class covariance table.
+// The kriging variance comes from the factorisation's Schur block (FP32).
+// Systems with a non-positive pivot are queued for the FP64 re-solve.
+#include "solver_refine.h"
+
+namespace okr {
+namespace {
+
+template <int NB, int UPD>
+__global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
+  __shared__ Smem<float> sm;
+  __shared__ MixedSmem msm;
+  const double tscale = 1.0 / a.sill;
+  block_setup<float>(a, sm, tscale);
+  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) msm.tc64[i] = a.tab.tc_d[i] * tscale;
+  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) msm.t064[i] = a.tab.t0_d[i] * tscale;
+  __syncthreads();
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  WaveScratch<float>& ws = sm.ws[wid];
+  MixedScratch& mx = msm.ms[wid];
+  const int nb = a.nb;
+  int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
+  if (nlo < 1) nlo = 1;
+  if (nhi > kHist - 1) nhi = kHist - 1;
+  if (nlo > nhi) return;
+  const unsigned long long start = a.ctr->offsets[nhi];
+  const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
+  unsigned long long* cursor = &a.ctr->cls_next[NB];
+  const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int d0 = sm.sdesc[lane];
+  const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
+  for (;;) {
+    unsigned long long base = 0;
+    if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
+    base = uniform64(base);
+    if (base >= end) break;
+    const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
+    Pipe q;
+    pipe_load(q, a, a.perm, base, nk);
+    pipe_prefetch(q, a, 0, d0, d1, below);
+    unsigned long long refined = 0;
+    for (int k = 0; k < nk; ++k) {
+      const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
+      const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
+      const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
+      pipe_commit<float>(q, ws, d0, d1);
+      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
+      const int n = __popcll(lo) + __popcll(hi);
+      double est = 0.0;
+      float var = 0.0f, mn, mxp;
+      bool bad;
+      mixed_system<NB, UPD>(n, nb, ws, sm, mx, msm, ncand, ntgt, a.sill, &est, &var, mn, mxp, bad);
+      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad);
+      if (lane == 0 && a.flags && !bad) a.flags[sys] |= kFlagRefined;
+      refined += bad ? 0 : 1;
+    }
+    if (lane == 0 && refined) atomicAdd(&a.ctr->refined, refined);
+  }
+}
+
+template <int UPD>
+hipError_t launch_mixed_classes(const SolveArgs& a, int grid, hipStream_t s) {
+  const int nbmax = (a.geo.ncand + a.nb + 15) / 16;
+#define OKR_CLS(K)                                                                            \
+  if (nbmax >= K) {                                                                           \
+    hipLaunchKernelGGL((mixed_class_kernel<K, UPD>), dim3(grid), dim3(256), 0, s, a);         \
+    hipError_t e = hipGetLastError();                                                         \
+    if (e != hipSuccess) return e;                                                            \
+  }
+  OKR_CLS(8) OKR_CLS(7) OKR_CLS(6) OKR_CLS(5) OKR_CLS(4) OKR_CLS(3) OKR_CLS(2) OKR_CLS(1)
+#undef OKR_CLS
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s) {
+  if (a.precision == 2) return launch_mixed_classes<2>(a, grid, s);
+  return launch_mixed_classes<1>(a, grid, s);
+}
+
+}  // namespace okr

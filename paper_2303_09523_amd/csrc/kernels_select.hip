@@ -81,6 +81,7 @@ __global__ void tables_kernel(Vario v, int f, int r, TableSet t) {
 
 __global__ void reset_kernel(DevCounters* c) {
   int i = threadIdx.x;
+  if (i <= kMaxBlocks) c->cls_next[i] = 0;
   if (i < kHist) {
     c->hist[i] = 0;
     c->cursor[i] = 0;
@@ -97,6 +98,15 @@ __global__ void reset_kernel(DevCounters* c) {
     c->nonfinite = 0;
     c->offsets[kHist] = 0;
     c->n_fallback_list = 0;
+  }
+}
+
+__global__ void reset_cursors_kernel(DevCounters* c) {
+  int i = threadIdx.x;
+  if (i <= kMaxBlocks) c->cls_next[i] = 0;
+  if (i == 0) {
+    c->next = 0;
+    c->next2 = 0;
   }
 }
 
@@ -254,6 +264,11 @@ hipError_t launch_tables(const Vario& v, const Geometry& g, TableSet t, hipStrea
 
 hipError_t launch_reset(DevCounters* c, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kHist), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_cursors(DevCounters* c, hipStream_t s) {
+  hipLaunchKernelGGL(reset_cursors_kernel, dim3(1), dim3(64), 0, s, c);
   return hipGetLastError();
 }
 

@@ -20,10 +20,6 @@ size_t plain_shared_bytes(const Geometry& g);
 hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, int ngaps,
                               const SelectRule& rule, uint64_t* bits, uint8_t* count,
                               DevCounters* c, hipStream_t s);
-hipError_t launch_loso_forward(const SolveArgs& a, const float* slices, double* sq, double* loss,
-                               int grid, hipStream_t s);
-hipError_t launch_loso_backward(const SolveArgs& a, const double* resid, double* partial,
-                                double* grad, int grid, hipStream_t s);
 }  // namespace okr
 
 struct okr_plan {
@@ -41,9 +37,9 @@ struct okr_plan {
   okr::DevCounters* ctr = nullptr;
   double* tabs = nullptr;       // FP64 tables and derivatives
   float* tabs_f = nullptr;      // FP32 copies
-  double* loso_sq = nullptr;    // per held-out voxel residual (z_hat - z)
-  double* loso_partial = nullptr;
-  double* loso_loss = nullptr;
+  double* loso_resid = nullptr;   // per held-out voxel residual (z_hat - z)
+  double* loso_gpart = nullptr;   // per held-out voxel gradient contribution [3]
+  double* loso_partial = nullptr; // reduction partials
   bool loso_ready = false;
   okr_variogram loso_vario{};
   const float* loso_slices = nullptr;
@@ -186,9 +182,9 @@ void free_plan(okr_plan* p) {
   hipFree(p->ctr);
   hipFree(p->tabs);
   hipFree(p->tabs_f);
-  hipFree(p->loso_sq);
+  hipFree(p->loso_resid);
+  hipFree(p->loso_gpart);
   hipFree(p->loso_partial);
-  hipFree(p->loso_loss);
   delete p;
 }
 
@@ -225,6 +221,10 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.precision = p->prob.precision;
   a.kappa_limit = 1e300;
   a.fallback = nullptr;
+  a.step = 1;
+  a.resid = nullptr;
+  a.gpart = nullptr;
+  a.inv_count = 0.0;
   return a;
 }
 
@@ -364,6 +364,7 @@ okr_status okr_execute(okr_plan* p, const okr_variogram* vario, const float* d_s
   if (st != OKR_OK) return fail(p, st, msg);
   if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
   const okr::Geometry& g = p->geo;
+  p->loso_ready = false;
   OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
   {
     PhaseTimer t(p, OKR_PHASE_PLACE);
@@ -397,13 +398,18 @@ okr_status okr_execute(okr_plan* p, const okr_variogram* vario, const float* d_s
   a.flags = d_flags;
   const char* force = std::getenv("OKR_FORCE_FALLBACK");
   const bool forced = force && force[0] == '1';
+  const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
+  if (mixed) a.fallback = p->fallback;   // systems with a non-positive pivot
   if (forced && p->prob.precision != OKR_FP64) {
     a.kappa_limit = 0.0;
     a.fallback = p->fallback;
   }
   {
     PhaseTimer t(p, OKR_PHASE_SOLVE);
-    OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), p->stream));
+    if (mixed)
+      OKR_HIP(p, okr::launch_solve_mixed(a, persistent_grid(p), p->stream));
+    else
+      OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), p->stream));
   }
   if (a.fallback) {
     PhaseTimer t(p, OKR_PHASE_FALLBACK);
@@ -433,14 +439,70 @@ okr_status okr_plan_set_profiling(okr_plan* p, int32_t enable) {
 okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float* d_slices,
                             const uint8_t* d_edge, double* d_loss) {
   if (!p) return OKR_E_INVALID_ARG;
-  (void)vario; (void)d_slices; (void)d_edge; (void)d_loss;
-  return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is not available in this build");
+  std::string msg;
+  okr_status st = validate_vario(vario, &msg);
+  if (st != OKR_OK) return fail(p, st, msg);
+  if (!d_slices || !d_loss) return fail(p, OKR_E_INVALID_ARG, "slices and loss are required");
+  if (p->prob.algo != OKR_ALGO_BATCHED)
+    return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out needs a batched plan");
+  if (p->geo.f != 2)
+    return fail(p, OKR_E_UNSUPPORTED,
+                "leave-one-slice-out uses the upsample-2 geometry (held-out slice half-way)");
+  if (p->geo.nslices < 3) return fail(p, OKR_E_SHAPE, "leave-one-slice-out needs >= 3 slices");
+  p->loso_ready = false;
+  okr::Geometry gl = p->geo;
+  gl.nsys = gl.plane * (gl.nslices - 2);
+  const size_t nl = (size_t)gl.nsys;
+  if (!p->loso_resid) {
+    if ((st = dev_alloc(p, &p->loso_resid, nl)) != OKR_OK) return st;
+    if ((st = dev_alloc(p, &p->loso_gpart, 3 * nl)) != OKR_OK) return st;
+    if ((st = dev_alloc(p, &p->loso_partial, 256 * 3)) != OKR_OK) return st;
+  }
+  PhaseTimer t(p, OKR_PHASE_LOSO);
+  OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_tables(vario_of(vario), gl, tables_of(p), p->stream));
+  OKR_HIP(p, okr::launch_select_step(d_edge, gl, 2, gl.nslices - 2, p->rule, p->bits, p->count,
+                                     p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_bucket(p->count, gl, p->perm, p->ctr, p->stream));
+  okr::SolveArgs a = solve_args(p, vario);
+  a.geo = gl;
+  a.slices = d_slices;
+  a.step = 2;
+  a.resid = p->loso_resid;
+  a.gpart = p->loso_gpart;
+  a.inv_count = 1.0 / (double)gl.nsys;
+  OKR_HIP(p, okr::launch_loso_forward(a, persistent_grid(p), p->stream));
+  OKR_HIP(p, okr::launch_reduce(p->loso_resid, gl.nsys, 1, a.inv_count, p->loso_partial, d_loss,
+                                true, p->stream));
+  p->loso_ready = true;
+  p->loso_vario = *vario;
+  p->loso_slices = d_slices;
+  p->loso_edge = d_edge;
+  p->last_nsys = gl.nsys;
+  p->last_kriged = gl.nsys;
+  return OKR_OK;
 }
 
 okr_status okr_loso_backward(okr_plan* p, double* d_grad) {
   if (!p) return OKR_E_INVALID_ARG;
-  (void)d_grad;
-  return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is not available in this build");
+  if (!d_grad) return fail(p, OKR_E_INVALID_ARG, "grad is required");
+  if (!p->loso_ready)
+    return fail(p, OKR_E_INVALID_ARG, "okr_loso_backward needs a preceding okr_loso_forward");
+  okr::Geometry gl = p->geo;
+  gl.nsys = gl.plane * (gl.nslices - 2);
+  PhaseTimer t(p, OKR_PHASE_LOSO);
+  okr::SolveArgs a = solve_args(p, &p->loso_vario);
+  a.geo = gl;
+  a.slices = p->loso_slices;
+  a.step = 2;
+  a.resid = p->loso_resid;
+  a.gpart = p->loso_gpart;
+  a.inv_count = 1.0 / (double)gl.nsys;
+  OKR_HIP(p, okr::launch_reset_cursors(p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_loso_backward(a, persistent_grid(p), p->stream));
+  OKR_HIP(p, okr::launch_reduce(p->loso_gpart, gl.nsys, 3, 1.0, p->loso_partial, d_grad, false,
+                                p->stream));
+  return OKR_OK;
 }
 
 okr_status okr_stats_get(okr_plan* p, okr_stats* out) {

@@ -59,12 +59,14 @@ struct DevCounters {
   unsigned long long offsets[kHist + 1];  // bucket starts (largest n first)
   unsigned long long cursor[kHist];
   unsigned long long next2;         // second-pass cursor
+  unsigned long long cls_next[kMaxBlocks + 1];  // per size-class cursors
   unsigned long long n_fallback_list;
 };
 
 // ---- launchers (kernels_select.hip) ----
 hipError_t launch_tables(const Vario& v, const Geometry& g, TableSet t, hipStream_t s);
 hipError_t launch_reset(DevCounters* c, hipStream_t s);
+hipError_t launch_reset_cursors(DevCounters* c, hipStream_t s);
 hipError_t launch_place(const float* slices, float* volume, float* variance, const Geometry& g,
                         DevCounters* c, hipStream_t s);
 hipError_t launch_select(const uint8_t* edge, const Geometry& g, const SelectRule& rule,
@@ -89,10 +91,27 @@ struct SolveArgs {
   int precision;        // okr_precision
   double kappa_limit;   // condition estimate above which a system is re-solved in FP64
   uint32_t* fallback;   // list of systems for the FP64 pass
+  int step;             // upper bounding slice = lower + step (1: volume, 2: held-out slice)
+  double* resid;        // leave-one-slice-out: z_hat - z per system
+  double* gpart;        // leave-one-slice-out: per-system gradient [3]
+  double inv_count;     // 1 / number of held-out voxels
 };
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t launch_solve_fallback(const SolveArgs& a, int grid, hipStream_t s);
 int solve_blocks_needed(const Geometry& g);
+
+hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
+
+// ---- launchers (kernels_adjoint.hip) ----
+hipError_t launch_loso_forward(const SolveArgs& a, int grid, hipStream_t s);
+hipError_t launch_loso_backward(const SolveArgs& a, int grid, hipStream_t s);
+// Deterministic sum of x[i*stride + comp] over i < n (fixed order), comp < ncomp,
+// scaled by `scale`, into out[comp]; partial needs 256 * ncomp doubles.
+hipError_t launch_reduce(const double* x, long long n, int ncomp, double scale, double* partial,
+                         double* out, bool square, hipStream_t s);
+hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, int ngaps,
+                              const SelectRule& rule, uint64_t* bits, uint8_t* count,
+                              DevCounters* c, hipStream_t s);
 
 // ---- launchers (kernels_plain.hip) ----
 hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume, float* variance,

@@ -1,0 +1,432 @@
+// Device-side building blocks of the batched kriging solvers (included by the
+// solver translation units; everything here is inlined into their kernels).
+//
+// See kernels_solve.hip for the method: the augmented matrix [[C, B], [B^T, 0]]
+// of one (column, gap) system in 16x16 register tiles, left-looking Cholesky
+// with MFMA updates, and the Schur read-out.
+#pragma once
+
+#include <type_traits>
+
+#include "okrig_internal.h"
+
+namespace okr {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct VecOf;
+template <> struct VecOf<float> { using type = f32x4; };
+template <> struct VecOf<double> { using type = f64x4; };
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// T += Q P^T, all three in lane-row layout.
+template <typename V>
+__device__ __forceinline__ V acc_qpt(V c, const V& q, const V& p) {
+  c = mfma4(p[0], q[0], c);
+  c = mfma4(p[1], q[1], c);
+  c = mfma4(p[2], q[2], c);
+  c = mfma4(p[3], q[3], c);
+  return c;
+}
+
+__device__ __forceinline__ float lane_value(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double lane_value(double x, int lane) {
+  long long b = __double_as_longlong(x);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long x, int lane) {
+  unsigned lo = __builtin_amdgcn_readlane((unsigned)(x & 0xffffffffu), lane);
+  unsigned hi = __builtin_amdgcn_readlane((unsigned)(x >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
+  unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(x & 0xffffffffu));
+  unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+constexpr int tix(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// 1/sqrt(x): the hardware reciprocal square root in FP32 (about 1 ulp, well
+// inside the FP32 factorisation error), the correctly rounded form in FP64.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
+// Tile column held by element v of lane group g (see the layout note above).
+template <typename T> __device__ __forceinline__ constexpr int colmap(int g, int v);
+template <> __device__ __forceinline__ constexpr int colmap<float>(int g, int v) { return 4 * g + v; }
+template <> __device__ __forceinline__ constexpr int colmap<double>(int g, int v) { return 4 * v + g; }
+// Lane group and element holding tile column c.
+template <typename T> __device__ __forceinline__ constexpr int colgroup(int c) {
+  return sizeof(T) == 4 ? (c >> 2) : (c & 3);
+}
+template <typename T> __device__ __forceinline__ constexpr int colelem(int c) {
+  return sizeof(T) == 4 ? (c & 3) : (c >> 2);
+}
+
+constexpr int kWaves = 4;
+constexpr int kChunk = 16;
+
+template <typename T>
+struct WaveScratch {
+  int desc[128];      // point descriptors in system order
+  float val[128];     // point values
+  T buf[16 * 17];     // tile transposes and the read-out
+};
+
+template <typename T> struct Smem {
+  T tc[kTcSize];
+  T t0[kT0Size];
+  int sdesc[128];
+  WaveScratch<T> ws[kWaves];
+};
+// FP32 blocks also keep the covariance of every candidate pair, so a matrix
+// entry is a single LDS read.
+template <> struct Smem<float> {
+  float tc[kTcSize];
+  float t0[kT0Size];
+  int sdesc[128];
+  WaveScratch<float> ws[kWaves];
+  float cc[kMaxCand * kMaxCand];
+};
+
+// Candidate descriptor: bits 0..6 candidate index; bits 8..15
+// (s<<6)|((dy+r)<<3)|(dx+r); bits 16..20 target-table column s*16+|dy|*4+|dx|.
+__device__ __forceinline__ int cand_desc(int c, int r, int W, int W2) {
+  int s = c >= W2;
+  int o = c - s * W2;
+  int a = o / W, b = o - a * W;
+  int ady = a > r ? a - r : r - a;
+  int adx = b > r ? b - r : r - b;
+  return c | (((s << 6) | (a << 3) | b) << 8) | ((s * 16 + ady * 4 + adx) << 16);
+}
+
+__device__ __forceinline__ int pair_class(int dp, int dq) {
+  const int cp = (dp >> 8) & 0xff, cq = (dq >> 8) & 0xff;
+  const int ddy = ((cp >> 3) & 7) - ((cq >> 3) & 7);
+  const int ddx = (cp & 7) - (cq & 7);
+  return ((cp ^ cq) & 64) | ((ddy < 0 ? -ddy : ddy) << 3) | (ddx < 0 ? -ddx : ddx);
+}
+
+template <typename T>
+__device__ __forceinline__ T cov_pair(int dp, int dq, const Smem<T>& sm, int ncand);
+template <>
+__device__ __forceinline__ float cov_pair<float>(int dp, int dq, const Smem<float>& sm, int ncand) {
+  return sm.cc[(dp & 0x7f) * ncand + (dq & 0x7f)];
+}
+template <>
+__device__ __forceinline__ double cov_pair<double>(int dp, int dq, const Smem<double>& sm, int) {
+  return sm.tc[pair_class(dp, dq)];
+}
+
+// Entry M[p][q] of the augmented matrix from the two indices' descriptors:
+//   >= 0: data point, -1: identity padding, <= -2: border row b = -2 - d.
+template <typename T>
+__device__ __forceinline__ T entry(int dp, int dq, float vp, float vq, bool same,
+                                   const Smem<T>& sm, int ncand) {
+  if (dp >= 0 && dq >= 0) return cov_pair<T>(dp, dq, sm, ncand);
+  if (dp == -1 || dq == -1) return same ? T(1) : T(0);
+  if (dp < -1 && dq < -1) return T(0);
+  int b, d;
+  float v;
+  if (dp < -1) {
+    b = -2 - dp; d = dq; v = vq;
+  } else {
+    b = -2 - dq; d = dp; v = vp;
+  }
+  if (b == 0) return T(1);
+  if (b == 1) return T(v);
+  return sm.t0[(b - 2) * kT0Stride + (d >> 16)];
+}
+
+// Left-looking factorisation of one system with NB blocks; leaves the last
+// diagonal tile (holding G in its border corner) in buf.
+template <typename T, int NB>
+__device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T>& ws,
+                                              const Smem<T>& sm, int ncand, T* buf, T& minpiv,
+                                              T& maxpiv, bool& bad) {
+  using V = typename VecOf<T>::type;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  constexpr int N = 16 * NB;
+  const int bstart = N - nb;
+  V L[NB * (NB + 1) / 2];
+  int rd[NB];
+  float rv[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int p = 16 * i + r;
+    rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
+    rv[i] = p < n ? ws.val[p] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    // keep each column's loads and updates together: hoisting later columns'
+    // table reads would hold them in registers for the whole factorisation
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- assemble block column j (negated) ----
+    int cd[4];
+    float cv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = 16 * j + colmap<T>(g, v);
+      cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
+      cv[v] = q < n ? ws.val[q] : 0.0f;
+    }
+    const bool colC = 16 * j + 16 <= n;
+#pragma unroll
+    for (int i = j; i < NB; ++i) {
+      V t;
+      if (colC && 16 * i + 16 <= n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t[v] = -cov_pair<T>(rd[i], cd[v], sm, ncand);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool same = (i == j) && (r == colmap<T>(g, v));
+          t[v] = -entry<T>(rd[i], cd[v], rv[i], cv[v], same, sm, ncand);
+        }
+      }
+      L[tix(i, j)] = t;
+    }
+    // ---- updates from the finished columns: S_ij += L_ik L_jk^T ----
+#pragma unroll
+    for (int k = 0; k < j; ++k) {
+#pragma unroll
+      for (int i = j; i < NB; ++i) L[tix(i, j)] = acc_qpt(L[tix(i, j)], L[tix(i, k)], L[tix(j, k)]);
+    }
+    // ---- diagonal tile ----
+    const int ne = (j == NB - 1) ? 16 - nb : 16;
+    V X;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[v] = (r == colmap<T>(g, v)) ? T(1) : T(0);
+    V D = L[tix(j, j)];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c < ne) {
+        const int g0 = colgroup<T>(c), v0 = colelem<T>(c);
+        T piv = -lane_value(D[v0], 16 * g0 + c);
+        if (!(piv > T(0)) || !isfinite(piv)) {
+          bad = true;
+          piv = T(1);
+        }
+        minpiv = piv < minpiv ? piv : minpiv;
+        maxpiv = piv > maxpiv ? piv : maxpiv;
+        const T is = inv_sqrt(piv);
+        const bool mine = (g == g0);
+        const T u = (mine && r > c) ? -D[v0] * is : T(0);
+        X[v0] = mine ? X[v0] * is : X[v0];
+        const T w = mine ? X[v0] : T(0);
+        D = mfma4(u, u, D);
+        X = mfma4(-u, w, X);
+      }
+    }
+    L[tix(j, j)] = D;
+    if (j < NB - 1) {
+      // Inv = transpose(X) through LDS, negated
+#pragma unroll
+      for (int v = 0; v < 4; ++v) buf[r * 17 + colmap<T>(g, v)] = X[v];
+      __builtin_amdgcn_wave_barrier();
+      V NI;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) NI[v] = -buf[colmap<T>(g, v) * 17 + r];
+      __builtin_amdgcn_wave_barrier();
+      // off-diagonal solve: L_ij = M_ij L_jj^{-T} = S_ij (-Inv)^T
+#pragma unroll
+      for (int i = j + 1; i < NB; ++i) {
+        V z = {T(0), T(0), T(0), T(0)};
+        L[tix(i, j)] = acc_qpt(z, L[tix(i, j)], NI);
+      }
+    }
+  }
+  const V& Lz = L[tix(NB - 1, NB - 1)];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) buf[r * 17 + colmap<T>(g, v)] = Lz[v];
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ void solve_system(int n, int nb, const WaveScratch<T>& ws, const Smem<T>& sm, int ncand,
+                             T* buf, T sill, int ntgt, T* est, T* var, T& minpiv, T& maxpiv,
+                             bool& bad) {
+  minpiv = T(3.0e38);
+  maxpiv = T(0);
+  bad = false;
+  factor_system<T, NB>(n, nb, ws, sm, ncand, buf, minpiv, maxpiv, bad);
+  const int lane = threadIdx.x & 63;
+  const int ne = 16 - nb;
+  if (lane < ntgt) {
+    const int t = lane + 1;
+    const T g11 = buf[ne * 17 + ne];
+    const T g1z = buf[ne * 17 + ne + 1];
+    const T g1t = buf[ne * 17 + ne + 1 + t];
+    const T gzt = buf[(ne + 1) * 17 + ne + 1 + t];
+    const T gtt = buf[(ne + 1 + t) * 17 + ne + 1 + t];
+    const T m = (T(1) - g1t) / g11;
+    *est = gzt + m * g1z;
+    *var = sill - gtt + (T(1) - g1t) * m;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T, int NBMAX>
+__device__ __forceinline__ void dispatch(int NB, int n, int nb, const WaveScratch<T>& ws,
+                                         const Smem<T>& sm, int ncand, T* buf, T sill, int ntgt,
+                                         T* est, T* var, T& mn, T& mx, bool& bad) {
+  switch (NB) {
+#define OKR_NB(K)                                                                      \
+  case K:                                                                              \
+    if constexpr (NBMAX >= K)                                                          \
+      solve_system<T, K>(n, nb, ws, sm, ncand, buf, sill, ntgt, est, var, mn, mx, bad); \
+    break;
+    OKR_NB(1) OKR_NB(2) OKR_NB(3) OKR_NB(4) OKR_NB(5) OKR_NB(6) OKR_NB(7) OKR_NB(8)
+#undef OKR_NB
+    default: break;
+  }
+}
+
+template <typename T>
+__device__ void init_block(const SolveArgs& a, Smem<T>& sm, double tscale) {
+  const double* tcs = a.tab.tc_d;
+  const double* t0s = a.tab.t0_d;
+  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) sm.tc[i] = T(tcs[i] * tscale);
+  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(t0s[i] * tscale);
+  for (int i = threadIdx.x; i < 128; i += blockDim.x)
+    sm.sdesc[i] = i < a.geo.ncand ? cand_desc(i, a.geo.r, a.geo.W, a.geo.W2) : 0;
+}
+
+__device__ __forceinline__ void atomic_max_float(unsigned int* addr, float v) {
+  if (v > 0.0f && isfinite(v)) atomicMax(addr, __float_as_uint(v));
+}
+
+
+// Metadata of up to kChunk systems (one per lane) and the one-system-ahead
+// prefetch of neighbour values.
+struct Pipe {
+  unsigned int msys = 0;
+  unsigned long long mlo = 0, mhi = 0;
+  int mcnt = 0;
+  float pv0 = 0.0f, pv1 = 0.0f;
+  int pp0 = -1, pp1 = -1;
+};
+
+__device__ __forceinline__ void pipe_load(Pipe& q, const SolveArgs& a, const uint32_t* list,
+                                          unsigned long long base, int nk) {
+  const int lane = threadIdx.x & 63;
+  if (lane < nk) {
+    q.msys = list[base + lane];
+    q.mlo = a.bits[2ull * q.msys];
+    q.mhi = a.bits[2ull * q.msys + 1];
+    q.mcnt = a.count[q.msys];
+  }
+}
+
+__device__ __forceinline__ void pipe_prefetch(Pipe& q, const SolveArgs& a, int k, int d0, int d1,
+                                              uint64_t below) {
+  const int lane = threadIdx.x & 63;
+  const Geometry& geo = a.geo;
+  const unsigned plane = (unsigned)geo.plane, nx = (unsigned)geo.nx;
+  const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
+  const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
+  const unsigned gap = sys / plane;
+  const unsigned pix = sys - gap * plane;
+  const unsigned y = pix / nx, x = pix - y * nx;
+  const int n0 = __popcll(lo);
+  q.pp0 = ((lo >> lane) & 1ull) ? __popcll(lo & below) : -1;
+  q.pp1 = (lane + 64 < geo.ncand && ((hi >> lane) & 1ull)) ? n0 + __popcll(hi & below) : -1;
+  if (q.pp0 >= 0) {
+    const int c = (d0 >> 8) & 0xff;
+    q.pv0 = a.slices[(long long)(gap + ((c >> 6) & 1) * a.step) * geo.plane +
+                     (long long)((int)y + ((c >> 3) & 7) - geo.r) * geo.nx +
+                     ((int)x + (c & 7) - geo.r)];
+  }
+  if (q.pp1 >= 0) {
+    const int c = (d1 >> 8) & 0xff;
+    q.pv1 = a.slices[(long long)(gap + ((c >> 6) & 1) * a.step) * geo.plane +
+                     (long long)((int)y + ((c >> 3) & 7) - geo.r) * geo.nx +
+                     ((int)x + (c & 7) - geo.r)];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pipe_commit(const Pipe& q, WaveScratch<T>& ws, int d0, int d1) {
+  if (q.pp0 >= 0) {
+    ws.desc[q.pp0] = d0;
+    ws.val[q.pp0] = q.pv0;
+  }
+  if (q.pp1 >= 0) {
+    ws.desc[q.pp1] = d1;
+    ws.val[q.pp1] = q.pv1;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Shared tables of a workgroup; covariances are multiplied by tscale (1, or
+// 1/sill for the scaled mixed-precision systems).
+template <typename T>
+__device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, double tscale = 1.0) {
+  init_block<T>(a, sm, tscale);
+  __syncthreads();
+  if constexpr (sizeof(T) == 4) {
+    // covariance of every candidate pair, rounded once from the FP64 table
+    const int nc = a.geo.ncand;
+    for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
+      const int p = i / nc, q = i - p * nc;
+      sm.cc[i] = (float)(a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale);
+    }
+    __syncthreads();
+  }
+}
+
+
+// Writes the estimates and variances of one system, or queues it for the
+// FP64 pass; updates flags and counters.
+template <typename T>
+__device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsigned sys, int cnt,
+                                              T est, T var, T mn, T mx, bool bad) {
+  const int lane = threadIdx.x & 63;
+  const Geometry& geo = a.geo;
+  const int ntgt = geo.f - 1;
+  const T kappa = mx / mn;
+  const bool fallback = mode == 0 && a.fallback && (bad || (double)kappa > a.kappa_limit);
+  const unsigned plane = (unsigned)geo.plane;
+  const unsigned gap = sys / plane;
+  const unsigned pix = sys - gap * plane;
+  if (fallback) {
+    if (lane == 0) {
+      const unsigned long long slot = atomicAdd(&a.ctr->n_fallback_list, 1ull);
+      a.fallback[slot] = sys;
+    }
+  } else if (lane < ntgt) {
+    const long long o = ((long long)gap * geo.f + lane + 1) * geo.plane + pix;
+    a.volume[o] = (float)est;
+    if (a.variance) a.variance[o] = (float)var;
+  }
+  if (lane == 0) {
+    uint8_t fl = (cnt & kFloorBit) ? kFlagFloor : 0;
+    if (mode == 1) fl |= kFlagFp64;
+    if (bad && mode == 0) fl |= kFlagBadPivot;
+    if (a.flags) {
+      if (mode == 0) a.flags[sys] = fl;
+      else a.flags[sys] |= fl;
+    }
+    if (bad && mode == 0) atomicAdd(&a.ctr->bad_pivot, 1ull);
+    if (mode == 1) atomicAdd(&a.ctr->fp64_fallback, 1ull);
+    atomic_max_float(&a.ctr->max_kappa_bits, (float)kappa);
+  }
+}
+
+}  // namespace
+}  // namespace okr

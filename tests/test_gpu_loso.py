@@ -1,0 +1,123 @@
+"""GPU leave-one-slice-out loss and adjoint gradient against the FP64 oracle,
+finite differences of the GPU loss, bitwise repeatability and Adam
+trajectories."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(n, ny, nx, seed=11):
+    v = W.Variogram("exponential", 0.02, 0.8, 5.0)
+    f, _ = W.gaussian_field((n, ny, nx), v, seed=seed)
+    return f.astype(np.float32)
+
+
+def _plan(s, r=2):
+    import paper_2303_09523_amd as P
+    n, ny, nx = s.shape
+    return P.Plan(nx, ny, n, 2, r, 4)
+
+
+@pytest.mark.parametrize("model,theta", [("exponential", (0.1, 1.0, 2.0)),
+                                         ("spherical", (0.05, 1.2, 4.5)),
+                                         ("gaussian", (0.2, 1.0, 3.0))])
+def test_loso_loss_and_grad_vs_oracle(model, theta):
+    import torch
+    s = _field(6, 23, 21)
+    L_o, g_o = O.loso_loss_grad(s, 2, (model, *theta))
+    plan = _plan(s)
+    st = torch.from_numpy(s).cuda()
+    loss = plan.loso_forward(st, (model, *theta))
+    grad = plan.loso_backward()
+    L, g = float(loss.item()), grad.cpu().numpy()
+    plan.close()
+    print(f"{model}: loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
+    assert abs(L - L_o) <= 1e-9 * abs(L_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-4, atol=1e-6 * np.abs(g_o).max())
+
+
+def test_loso_grad_vs_gpu_finite_differences():
+    import torch
+    s = _field(5, 20, 22, seed=3)
+    plan = _plan(s)
+    st = torch.from_numpy(s).cuda()
+    th = np.array([0.1, 1.0, 2.0])
+    plan.loso_forward(st, ("exponential", *th))
+    g = plan.loso_backward().cpu().numpy()
+    fd = np.zeros(3)
+    h = 1e-4
+    for k in range(3):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        lp = float(plan.loso_forward(st, ("exponential", *tp)).item())
+        lm = float(plan.loso_forward(st, ("exponential", *tm)).item())
+        fd[k] = (lp - lm) / (2 * h)
+    plan.close()
+    print("adjoint", g, "fd", fd, flush=True)
+    np.testing.assert_allclose(g, fd, rtol=1e-4, atol=1e-6 * np.abs(fd).max())
+    # only nugget/sill and range matter: n dL/dn + s dL/ds = 0
+    assert abs(th[0] * g[0] + th[1] * g[1]) <= 1e-5 * np.abs(g).max()
+
+
+def test_loso_bitwise_repeatable():
+    import torch
+    s = _field(6, 31, 29, seed=5)
+    plan = _plan(s)
+    st = torch.from_numpy(s).cuda()
+    out = []
+    for _ in range(2):
+        L = plan.loso_forward(st, ("exponential", 0.05, 0.9, 4.0)).cpu().numpy()
+        g = plan.loso_backward().cpu().numpy()
+        out.append((L.tobytes(), g.tobytes()))
+    plan.close()
+    assert out[0] == out[1]
+
+
+def test_loso_backward_requires_forward():
+    import torch
+    import paper_2303_09523_amd as P
+    s = _field(4, 9, 9)
+    plan = _plan(s)
+    with pytest.raises(P.OkrError):
+        plan.loso_backward()
+    plan.close()
+
+
+def test_adam_trajectory_vs_oracle():
+    import torch
+    from paper_2303_09523_amd.autograd import fit_variogram
+    s = _field(5, 18, 17, seed=7)
+    plan = _plan(s)
+    st = torch.from_numpy(s).cuda()
+    steps = 25
+    traj = fit_variogram(plan, st, (0.1, 1.0, 2.0), steps=steps, lr=0.05)
+    plan.close()
+    ref = O.adam_fit(lambda th: O.loso_loss_grad(s, 2, ("exponential", *th)), (0.1, 1.0, 2.0),
+                     steps=steps, lr=0.05)
+    (Lg, tg), (Lr, tr) = traj[-1], ref[-1]
+    print("gpu", Lg, tg, "oracle", Lr, tr, flush=True)
+    assert abs(Lg - Lr) <= 1e-4 * abs(Lr)
+    np.testing.assert_allclose(tg, tr, rtol=1e-3)
+
+
+@pytest.mark.slow
+def test_loso_full_size_vs_oracle():
+    """The differentiation workload at full size (16 slices of 128x128)."""
+    import torch
+    w = W.workload("loso_16x128")
+    s, _ = W.make_inputs(w)
+    th = ("exponential", 0.1, 1.0, 2.0)
+    L_o, g_o = O.loso_loss_grad(s, 2, th)
+    plan = _plan(s)
+    st = torch.from_numpy(s).cuda()
+    L = float(plan.loso_forward(st, th).item())
+    g = plan.loso_backward().cpu().numpy()
+    plan.close()
+    print(f"full: loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
+    assert abs(L - L_o) <= 1e-9 * abs(L_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-4)
