@@ -1,9 +1,11 @@
 """Benchmark: kriged voxels/s of the batched edge-preserved kriging path.
 
 One step = one okr_execute over the whole synthetic volume: placement, table
-build, neighbour selection, size bucketing and the persistent batched solve
-(plus the FP64 re-solve pass of the mixed precision modes). Inputs are
-resident in HBM before timing starts.
+build, neighbour selection, size bucketing and the batched solve (one
+persistent launch per 16-wide size class, largest first) with, in the default
+mixed_fp16 precision, split-FP16 MFMA factorisation, back-substitution and the
+FP64 residual correction of every estimate, plus the FP64 re-solve of systems
+with a non-positive pivot. Inputs are resident in HBM before timing starts.
 
 Prints ONE JSON line. Extra keys:
   roofline       dominant kernel (batched solve): algorithmic FLOP per launch
@@ -11,7 +13,10 @@ Prints ONE JSON line. Extra keys:
   cpu_baseline   the FP64 oracle on a bounded random sample of the same
                  systems, on this host's cores
   plain_fp32     the per-voxel comparison kernel on a slab of the volume
+  batched_fp32   the batched path with FP32 factorisation (no correction)
   accuracy       GPU result vs the oracle on that same sample
+  loso           leave-one-slice-out loss + adjoint gradient timing on the
+                 16 x 128^2 field workload
 """
 from __future__ import annotations
 
@@ -87,10 +92,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_160x512")
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="mixed_fp16")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and LOSO extras")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="after timing, copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -146,30 +154,89 @@ def main():
     flops = float((hist * system_flops(nn, w.upsample)).sum())
     solve_ms = stats["phase_ms"]["solve"] / max(1, stats["phase_calls"]["solve"])
     achieved = flops / (solve_ms * 1e-3) / 1e12
+    # the factorisation's diagonal tiles, off-diagonal solves and back-substitution
+    # run on FP32 MFMA in every mode but fp64, and dominate its MFMA cycles
     peak = PEAKS["fp64_tflops"] if args.precision == "fp64" else PEAKS["fp32_tflops"]
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": None,
-            "kernel": "solve_kernel (batched Cholesky + read-out)",
+            "kernel": "batched solve (all size-class launches of one step)",
             "flop_per_launch": flops, "mean_launch_ms": round(solve_ms, 4)}
 
-    acc = None
-    if sample is not None:
+    def accuracy(vol_t, var_t):
+        if sample is None:
+            return None
         idx, est_o, var_o = sample
         plane = w.m * w.m
         g, p = idx // plane, idx % plane
         zs = g[:, None] * w.upsample + np.arange(1, w.upsample)[None, :]
-        vg = vol.cpu().numpy()
-        sg = var.cpu().numpy()
         yy, xx = (p // w.m)[:, None], (p % w.m)[:, None]
-        ge = vg[zs, yy, xx].astype(np.float64)
-        gv = sg[zs, yy, xx].astype(np.float64)
+        zt = torch.from_numpy(zs).to(dev)
+        yt = torch.from_numpy(np.broadcast_to(yy, zs.shape).copy()).to(dev)
+        xt = torch.from_numpy(np.broadcast_to(xx, zs.shape).copy()).to(dev)
+        ge = vol_t[zt, yt, xt].double().cpu().numpy()
+        gv = var_t[zt, yt, xt].double().cpu().numpy()
         zmax = float(np.abs(s).max())
         ee = np.abs(ge - est_o) / np.maximum(np.abs(est_o), 0.01 * zmax)
         evv = np.abs(gv - var_o) / w.vario.sill
-        acc = {"voxels": int(ee.size), "max_rel_err_est": float(ee.max()),
-               "p9999_rel_err_est": float(np.percentile(ee, 99.99)),
-               "max_rel_err_var": float(evv.max()),
-               "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max())}
+        return {"voxels": int(ee.size), "max_rel_err_est": float(ee.max()),
+                "p9999_rel_err_est": float(np.percentile(ee, 99.99)),
+                "max_rel_err_var": float(evv.max()),
+                "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max())}
+
+    acc = accuracy(vol, var)
+    calib = None
+    if args.calib_copy > 0:
+        src = torch.empty(args.calib_copy // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"copy_bytes": int(src.numel() * 4)}
+        del src, dst
+
+    extra_fp32 = None
+    loso = None
+    if not args.no_extra:
+        if args.precision != "fp32":
+            p32 = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, "fp32", "batched")
+            p32.execute(st, w.vario, et, volume=vol, variance=var)
+            torch.cuda.synchronize()
+            b0 = torch.cuda.Event(enable_timing=True)
+            b1 = torch.cuda.Event(enable_timing=True)
+            b0.record()
+            for _ in range(2):
+                p32.execute(st, w.vario, et, volume=vol, variance=var)
+            b1.record()
+            torch.cuda.synchronize()
+            ms32 = b0.elapsed_time(b1) / 2
+            extra_fp32 = {"value": kriged / (ms32 * 1e-3), "unit": "voxels/s",
+                          "ms_per_step": round(ms32, 3), "accuracy": accuracy(vol, var)}
+            p32.close()
+        wl = W.workload("loso_16x128")
+        sl_, _ = W.make_inputs(wl)
+        slt = torch.from_numpy(sl_).to(dev)
+        pl = P.Plan(wl.m, wl.m, wl.nslices, 2, wl.radius, 4)
+        th = ("exponential", 0.1, 1.0, 2.0)
+        pl.loso_forward(slt, th)
+        pl.loso_backward()
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c2 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(3):
+            pl.loso_forward(slt, th)
+        c1.record()
+        for _ in range(3):
+            pl.loso_backward()
+        c2.record()
+        torch.cuda.synchronize()
+        fms, bms = c0.elapsed_time(c1) / 3, c1.elapsed_time(c2) / 3
+        nvox = (wl.nslices - 2) * wl.m * wl.m
+        loso = {"workload": wl.name, "held_out_voxels": nvox, "forward_ms": round(fms, 3),
+                "backward_ms": round(bms, 3),
+                "loss_grad_evals_per_s": round(1000.0 / (fms + bms), 2)}
+        pl.close()
 
     plain = None
     if not args.no_plain:
@@ -196,10 +263,12 @@ def main():
     plan.close()
 
     out = {
-        "metric": "kriged voxels/sec (batched edge-preserved kriging, one MI355X)",
+        "metric": "kriged voxels/sec, batched mixed vs plain FP32 at <=1e-5 rel err; % roofline",
         "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64"}.get(
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64",
+                                                      "mixed_fp16": "f16x3+f32+f64corr",
+                                                      "mixed_bf16": "bf16x3+f32+f64corr"}.get(
             args.precision, args.precision),
         "data": "synthetic",
         "config": {"workload": w.name, "known_slices": w.nslices, "slice": f"{w.m}x{w.m}",
@@ -211,7 +280,10 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp32": plain,
+        "batched_fp32": extra_fp32,
         "accuracy": acc,
+        "loso": loso,
+        "calibration": calib,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in stats["phase_ms"].items()},
         "host_wall_s": round(t_host, 3),
     }
