@@ -51,6 +51,8 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int d0 = sm.sdesc[lane];
   const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
+  Tally tally;
+  unsigned long long refined = 0;
   for (;;) {
     unsigned long long base = 0;
     if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
@@ -60,7 +62,6 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
     pipe_prefetch(q, a, 0, d0, d1, below);
-    unsigned long long refined = 0;
     for (int k = 0; k < nk; ++k) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
@@ -72,12 +73,13 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
       float var = 0.0f, mn, mxp;
       bool bad;
       mixed_system<NB, UPD>(n, nb, ws, sm, mx, msm, ncand, ntgt, a.sill, &est, &var, mn, mxp, bad);
-      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad);
+      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally);
       if (lane == 0 && a.flags && !bad) a.flags[sys] |= kFlagRefined;
       refined += bad ? 0 : 1;
     }
-    if (lane == 0 && refined) atomicAdd(&a.ctr->refined, refined);
   }
+  flush_tally(a, tally);
+  if (lane == 0 && refined) atomicAdd(&a.ctr->refined, refined);
 }
 
 template <int UPD>

@@ -67,6 +67,7 @@ void solve_class_kernel(SolveArgs a) {
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int d0 = sm.sdesc[lane];
   const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
+  Tally tally;
   for (;;) {
     unsigned long long base = 0;
     if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
@@ -86,9 +87,10 @@ void solve_class_kernel(SolveArgs a) {
       T est = 0, var = 0, mn, mx;
       bool bad;
       solve_system<T, NB>(n, nb, ws, sm, ncand, ws.buf, sill, ntgt, &est, &var, mn, mx, bad);
-      finish_system<T>(a, 0, sys, cnt, est, var, mn, mx, bad);
+      finish_system<T>(a, 0, sys, cnt, est, var, mn, mx, bad, tally);
     }
   }
+  flush_tally(a, tally);
 }
 
 // FP64 re-solve of the queued systems (any size class).
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(256) void solve_list_kernel(SolveArgs a) {
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int d0 = sm.sdesc[lane];
   const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
+  Tally tally;
   for (;;) {
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&a.ctr->next2, (unsigned long long)kChunk);
@@ -124,9 +127,10 @@ __global__ __launch_bounds__(256) void solve_list_kernel(SolveArgs a) {
       T est = 0, var = 0, mn, mx;
       bool bad;
       dispatch<T, NBMAX>(NB, n, a.nb, ws, sm, ncand, ws.buf, sill, ntgt, &est, &var, mn, mx, bad);
-      finish_system<T>(a, 1, sys, cnt, est, var, mn, mx, bad);
+      finish_system<T>(a, 1, sys, cnt, est, var, mn, mx, bad, tally);
     }
   }
+  flush_tally(a, tally);
 }
 
 template <typename T>

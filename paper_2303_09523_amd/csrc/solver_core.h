@@ -151,6 +151,129 @@ __device__ __forceinline__ T entry(int dp, int dq, float vp, float vq, bool same
   return sm.t0[(b - 2) * kT0Stride + (d >> 16)];
 }
 
+// Pivot of one column: records the range of pivots and replaces a pivot that
+// is not positive and finite by 1 (the system is then flagged).
+template <typename T>
+__device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) {
+  if (!(piv > T(0)) || !isfinite(piv)) {
+    bad = true;
+    piv = T(1);
+  }
+  minpiv = piv < minpiv ? piv : minpiv;
+  maxpiv = piv > maxpiv ? piv : maxpiv;
+  return piv;
+}
+
+// Cholesky of one diagonal tile over its first ne columns, in four panels of
+// four columns. D is the negated tile (-A); on return its lower triangle holds
+// the trailing Schur complement (negated) of the columns >= ne, and X holds
+// L^{-T} in the lane-row layout (for ne < 16: the partial inverse of the
+// eliminated columns applied to the rest). Inside a panel the columns are
+// eliminated one by one on the vector ALUs; the rest of the tile then takes
+// the panel's rank-4 update with one MFMA (and one more for X), instead of
+// four rank-1 MFMAs. Entries above the diagonal are not kept up to date.
+//
+// FP32 layout: the panel's four columns sit in one lane group (elements 0..3),
+// so the in-panel work is lane-local and the MFMA operand (column k of the
+// panel in lane group k) goes through LDS.
+__device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* buf, float& minpiv,
+                                            float& maxpiv, bool& bad) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (4 * p < ne) {
+      const bool mine = (g == p);
+      f32x4 P;
+#pragma unroll
+      for (int v0 = 0; v0 < 4; ++v0) {
+        const int c = 4 * p + v0;
+        if (c < ne) {
+          const float piv = take_pivot(-lane_value(D[v0], 16 * p + c), minpiv, maxpiv, bad);
+          const float is = inv_sqrt(piv);
+          const float l = (r > c) ? -D[v0] * is : 0.0f;   // L[r][c] in the panel's lanes
+          P[v0] = l;
+          X[v0] = mine ? X[v0] * is : X[v0];
+#pragma unroll
+          for (int v1 = v0 + 1; v1 < 4; ++v1) {
+            const float s = lane_value(l, 16 * p + 4 * p + v1);   // L[c1][c]
+            D[v1] = mine ? D[v1] + l * s : D[v1];
+            X[v1] = mine ? X[v1] - X[v0] * s : X[v1];
+          }
+        } else {
+          P[v0] = 0.0f;
+        }
+      }
+      if (p < 3) {
+        if (mine) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            buf[r * 4 + v] = P[v];
+            buf[64 + r * 4 + v] = X[v];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        const float u = (r >= 4 * p + 4) ? buf[r * 4 + g] : 0.0f;   // L[r][4p+g]
+        const float xw = buf[64 + r * 4 + g];                        // X[r][4p+g]
+        __builtin_amdgcn_wave_barrier();
+        D = mfma4(u, u, D);
+        X = mfma4(-u, xw, X);
+      }
+    }
+  }
+}
+
+// FP64 layout: the panel's columns 4p+k sit in element p of lane group k, which
+// is already the MFMA operand layout; the in-panel updates take each column
+// from its lane group with a cross-lane shuffle.
+__device__ __forceinline__ void diag_factor(f64x4& D, f64x4& X, int ne, double* buf, double& minpiv,
+                                            double& maxpiv, bool& bad) {
+  (void)buf;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) X[v] = (r == 4 * v + g) ? 1.0 : 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    if (4 * p < ne) {
+      double u = 0.0;
+#pragma unroll
+      for (int k0 = 0; k0 < 4; ++k0) {
+        const int c = 4 * p + k0;
+        if (c < ne) {
+          const bool mine = (g == k0);
+          const double piv = take_pivot(-lane_value(D[p], 16 * k0 + c), minpiv, maxpiv, bad);
+          const double is = inv_sqrt(piv);
+          const double l = (r > c) ? -D[p] * is : 0.0;   // L[r][c] in lane group k0
+          X[p] = mine ? X[p] * is : X[p];
+          u = mine ? l : u;
+          if (k0 < 3) {
+            const double lb = __shfl(l, 16 * k0 + r, 64);
+            const double xb = __shfl(X[p], 16 * k0 + r, 64);
+            double s = 0.0;   // L[4p+g][c] for the later columns of the panel
+#pragma unroll
+            for (int k1 = k0 + 1; k1 < 4; ++k1) {
+              const double sk = lane_value(l, 16 * k0 + 4 * p + k1);
+              s = (g == k1) ? sk : s;
+            }
+            const bool later = g > k0;
+            D[p] = later ? D[p] + lb * s : D[p];
+            X[p] = later ? X[p] - xb * s : X[p];
+          }
+        }
+      }
+      if (p < 3) {
+        const double ut = (r >= 4 * p + 4) ? u : 0.0;
+        const double xw = X[p];
+        D = mfma4(ut, ut, D);
+        X = mfma4(-ut, xw, X);
+      }
+    }
+  }
+}
+
 // Left-looking factorisation of one system with NB blocks; leaves the last
 // diagonal tile (holding G in its border corner) in buf.
 template <typename T, int NB>
@@ -210,29 +333,8 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     // ---- diagonal tile ----
     const int ne = (j == NB - 1) ? 16 - nb : 16;
     V X;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[v] = (r == colmap<T>(g, v)) ? T(1) : T(0);
     V D = L[tix(j, j)];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      if (c < ne) {
-        const int g0 = colgroup<T>(c), v0 = colelem<T>(c);
-        T piv = -lane_value(D[v0], 16 * g0 + c);
-        if (!(piv > T(0)) || !isfinite(piv)) {
-          bad = true;
-          piv = T(1);
-        }
-        minpiv = piv < minpiv ? piv : minpiv;
-        maxpiv = piv > maxpiv ? piv : maxpiv;
-        const T is = inv_sqrt(piv);
-        const bool mine = (g == g0);
-        const T u = (mine && r > c) ? -D[v0] * is : T(0);
-        X[v0] = mine ? X[v0] * is : X[v0];
-        const T w = mine ? X[v0] : T(0);
-        D = mfma4(u, u, D);
-        X = mfma4(-u, w, X);
-      }
-    }
+    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad);
     L[tix(j, j)] = D;
     if (j < NB - 1) {
       // Inv = transpose(X) through LDS, negated
@@ -270,9 +372,9 @@ __device__ __forceinline__ void solve_system(int n, int nb, const WaveScratch<T>
   if (lane < ntgt) {
     const int t = lane + 1;
     const T g11 = buf[ne * 17 + ne];
-    const T g1z = buf[ne * 17 + ne + 1];
-    const T g1t = buf[ne * 17 + ne + 1 + t];
-    const T gzt = buf[(ne + 1) * 17 + ne + 1 + t];
+    const T g1z = buf[(ne + 1) * 17 + ne];
+    const T g1t = buf[(ne + 1 + t) * 17 + ne];
+    const T gzt = buf[(ne + 1 + t) * 17 + ne + 1];
     const T gtt = buf[(ne + 1 + t) * 17 + ne + 1 + t];
     const T m = (T(1) - g1t) / g11;
     *est = gzt + m * g1z;
@@ -391,11 +493,26 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
 }
 
 
+// Per-wave tallies of the finished systems, flushed to the counters once per
+// wave (one atomic per wave instead of one per system).
+struct Tally {
+  float kmax = 0.0f;
+  unsigned bad = 0, fp64 = 0;
+};
+
+__device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) {
+  if ((threadIdx.x & 63) == 0) {
+    if (t.bad) atomicAdd(&a.ctr->bad_pivot, (unsigned long long)t.bad);
+    if (t.fp64) atomicAdd(&a.ctr->fp64_fallback, (unsigned long long)t.fp64);
+    atomic_max_float(&a.ctr->max_kappa_bits, t.kmax);
+  }
+}
+
 // Writes the estimates and variances of one system, or queues it for the
-// FP64 pass; updates flags and counters.
+// FP64 pass; updates flags and the wave's tallies.
 template <typename T>
 __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsigned sys, int cnt,
-                                              T est, T var, T mn, T mx, bool bad) {
+                                              T est, T var, T mn, T mx, bool bad, Tally& tally) {
   const int lane = threadIdx.x & 63;
   const Geometry& geo = a.geo;
   const int ntgt = geo.f - 1;
@@ -414,18 +531,17 @@ __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsi
     a.volume[o] = (float)est;
     if (a.variance) a.variance[o] = (float)var;
   }
-  if (lane == 0) {
+  if (lane == 0 && a.flags) {
     uint8_t fl = (cnt & kFloorBit) ? kFlagFloor : 0;
     if (mode == 1) fl |= kFlagFp64;
     if (bad && mode == 0) fl |= kFlagBadPivot;
-    if (a.flags) {
-      if (mode == 0) a.flags[sys] = fl;
-      else a.flags[sys] |= fl;
-    }
-    if (bad && mode == 0) atomicAdd(&a.ctr->bad_pivot, 1ull);
-    if (mode == 1) atomicAdd(&a.ctr->fp64_fallback, 1ull);
-    atomic_max_float(&a.ctr->max_kappa_bits, (float)kappa);
+    if (mode == 0) a.flags[sys] = fl;
+    else a.flags[sys] |= fl;
   }
+  if (bad && mode == 0) tally.bad += 1;
+  if (mode == 1) tally.fp64 += 1;
+  const float kf = (float)kappa;
+  if (kf > tally.kmax && isfinite(kf)) tally.kmax = kf;
 }
 
 }  // namespace

@@ -181,29 +181,8 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     // diagonal tile
     const int ne = (j == NB - 1) ? 16 - nb : 16;
     f32x4 X;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
     f32x4 D = S[j];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      if (c < ne) {
-        const int g0 = c >> 2, v0 = c & 3;
-        float piv = -lane_value(D[v0], 16 * g0 + c);
-        if (!(piv > 0.0f) || !isfinite(piv)) {
-          bad = true;
-          piv = 1.0f;
-        }
-        minpiv = piv < minpiv ? piv : minpiv;
-        maxpiv = piv > maxpiv ? piv : maxpiv;
-        const float is = inv_sqrt(piv);
-        const bool mine = (g == g0);
-        const float u = (mine && r > c) ? -D[v0] * is : 0.0f;
-        X[v0] = mine ? X[v0] * is : X[v0];
-        const float w = mine ? X[v0] : 0.0f;
-        D = mfma4(u, u, D);
-        X = mfma4(-u, w, X);
-      }
-    }
+    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad);
     Xs[j] = X;
     if (j < NB - 1) {
       const f32x4 NI = neg_transpose(X, buf);
@@ -352,7 +331,7 @@ __device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& 
   if (lane < ntgt) {
     const int t = lane + 1;
     const float g11 = ws.buf[ne * 17 + ne];
-    const float g1t = ws.buf[ne * 17 + ne + 1 + t];
+    const float g1t = ws.buf[(ne + 1 + t) * 17 + ne];
     const float gtt = ws.buf[(ne + 1 + t) * 17 + ne + 1 + t];
     const float m = (1.0f - g1t) / g11;
     *var_out = (float)(sill * (double)(1.0f - gtt + (1.0f - g1t) * m));
