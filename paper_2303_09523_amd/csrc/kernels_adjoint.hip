@@ -26,12 +26,11 @@ struct AdjSmem {
 template <int NB, bool BACKWARD>
 __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   __shared__ Smem<float> sm;
-  __shared__ MixedSmem msm;
+  __shared__ LosoSmem msm;
   __shared__ AdjSmem as;
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
-  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) msm.tc64[i] = a.tab.tc_d[i] * tscale;
-  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) msm.t064[i] = a.tab.t0_d[i] * tscale;
+  mixed_setup(a, sm, msm, tscale);
   if (BACKWARD) {
     for (int i = threadIdx.x; i < 3 * kTcSize; i += blockDim.x)
       as.dtc[i / kTcSize][i % kTcSize] = a.tab.dtc_d[i];
@@ -74,7 +73,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
       double est = 0.0, zscale = 1.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      mixed_system<NB, 0>(n, nb, ws, sm, mx, msm, ncand, 1, a.sill, &est, &var, mn, mxp, bad,
+      mixed_system<NB, 0, LosoSmem>(n, nb, ws, sm, mx, msm, ncand, 1, a.sill, &est, &var, mn, mxp, bad,
                           BACKWARD ? wv : nullptr, &zscale);
       est = __shfl(est, 0, 64);
       const unsigned gap = sys / plane;
@@ -92,27 +91,31 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
         const double e = 2.0 * a.resid[sys] * a.inv_count;
         const double fac = e * zscale / a.sill;
         const int p0 = lane, p1 = lane + 64;
-        const double nu0 = p0 < n ? fac * mx.nu[p0] : 0.0;
-        const double nu1 = p1 < n ? fac * mx.nu[p1] : 0.0;
         const int e0 = p0 < n ? ws.desc[p0] : 0, e1 = p1 < n ? ws.desc[p1] : 0;
+        const double nu0 = p0 < n ? fac * mx.nuc[e0 & 0x7f] : 0.0;
+        const double nu1 = p1 < n ? fac * mx.nuc[e1 & 0x7f] : 0.0;
+        const uint8_t* row0 = msm.row(e0 & 0x7f);
+        const uint8_t* row1 = msm.row(e1 & 0x7f);
         double dcw0[3] = {0, 0, 0}, dcw1[3] = {0, 0, 0};
         for (int qq = 0; qq < n; ++qq) {
-          const int dq = ws.desc[qq];
+          const int cq = ws.desc[qq] & 0x7f;
           const double wq = wv[qq];
-          const int c0 = pair_class(e0, dq), c1 = pair_class(e1, dq);
+          const int c0 = row0[cq], c1 = row1[cq];
 #pragma unroll
           for (int kk = 0; kk < 3; ++kk) {
             dcw0[kk] += as.dtc[kk][c0] * wq;
             dcw1[kk] += as.dtc[kk][c1] * wq;
           }
         }
+        double gk[3];
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
           const double t0 = p0 < n ? as.dt0[kk][e0 >> 16] : 0.0;
           const double t1 = p1 < n ? as.dt0[kk][e1 >> 16] : 0.0;
-          const double gk = wave_sum_d(nu0 * (t0 - dcw0[kk]) + nu1 * (t1 - dcw1[kk]));
-          if (lane == 0) a.gpart[3ull * sys + kk] = gk;
+          gk[kk] = nu0 * (t0 - dcw0[kk]) + nu1 * (t1 - dcw1[kk]);
         }
+        wave_sums(gk);
+        if (lane < 3) a.gpart[3ull * sys + lane] = lane == 0 ? gk[0] : (lane == 1 ? gk[1] : gk[2]);
       }
     }
   }

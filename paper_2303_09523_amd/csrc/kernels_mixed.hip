@@ -33,8 +33,7 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
   __shared__ MixedSmem msm;
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
-  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) msm.tc64[i] = a.tab.tc_d[i] * tscale;
-  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) msm.t064[i] = a.tab.t0_d[i] * tscale;
+  mixed_setup(a, sm, msm, tscale);
   __syncthreads();
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveScratch<float>& ws = sm.ws[wid];

@@ -203,7 +203,7 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
 // tile of X^T, Z_I = (Y_I - sum_{K>I} Z_K L_KI) L_II^{-1}, Y the border rows of
 // L. For the last block, Z is minus the border rows of its partial inverse.
 // Row ne + b of the Z tiles holds x_b (b = 0: C^{-1} 1, 1: C^{-1} z,
-// 1 + t: C^{-1} c0_t); write_row copies one of them to LDS.
+// 1 + t: C^{-1} c0_t); write_rows copies them to LDS.
 template <int NB, int UPD>
 __device__ __forceinline__ void back_substitute(int nb, const PairStore<UPD> (&Ls)[NB][(NB + 1) / 2],
                                                 const f32x4 (&Xs)[NB], float* buf, f32x4 (&Z)[NB]) {
@@ -231,11 +231,16 @@ __device__ __forceinline__ void back_substitute(int nb, const PairStore<UPD> (&L
   }
 }
 
+// Rows row0 .. row0 + count - 1 of the Z tiles (one value per point) to slots
+// slot0 .. slot0 + count - 1 of x.
 template <int NB>
-__device__ __forceinline__ void write_row(const f32x4 (&Z)[NB], int row, float* dst) {
+__device__ __forceinline__ void write_rows(const f32x4 (&Z)[NB], int row0, int count, int slot0,
+                                           float (*x)[128]) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  if (r == row) {
+  const int k = r - row0;
+  if (k >= 0 && k < count) {
+    float* dst = x[slot0 + k];
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
 #pragma unroll
@@ -245,60 +250,144 @@ __device__ __forceinline__ void write_row(const f32x4 (&Z)[NB], int row, float* 
   __builtin_amdgcn_wave_barrier();
 }
 
-// ---- FP64 helpers (wave-wide) ----
-__device__ __forceinline__ double wave_sum_d(double x) {
+// ---- wave-wide reductions in a fixed order (the results are uniform) ----
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_ror:4 and row_ror:8
+// give every lane its 16-lane row's sum; the four row sums are then read from
+// lanes 0, 16, 32 and 48.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sums(double (&x)[K]) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  for (int k = 0; k < K; ++k) x[k] += dpp_d<0xB1>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_d<0x4E>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_d<0x124>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_d<0x128>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    x[k] = (lane_value(x[k], 0) + lane_value(x[k], 16)) + (lane_value(x[k], 32) + lane_value(x[k], 48));
 }
 
-// FP64 covariance of a pair from the pair-class table.
-__device__ __forceinline__ double cov64(int dp, int dq, const double* tc64) {
-  return tc64[pair_class(dp, dq)];
+__device__ __forceinline__ double wave_sum_d(double x) {
+  double s[1] = {x};
+  wave_sums(s);
+  return s[0];
 }
 
-// (C v)_p for the lane's points p = lane, lane + 64 (FP64; C from the FP64
-// class table; v in LDS).
-__device__ __forceinline__ void matvec64(int n, const int* desc, const double* v, const double* tc64,
-                                         double& out0, double& out1) {
-  const int lane = threadIdx.x & 63;
-  const int d0 = lane < n ? desc[lane] : 0;
-  const int d1 = lane + 64 < n ? desc[lane + 64] : 0;
-  double a0 = 0.0, a1 = 0.0;
-  for (int q = 0; q < n; ++q) {
-    const int dq = desc[q];
-    const double vq = v[q];
-    a0 += cov64(d0, dq, tc64) * vq;
-    a1 += cov64(d1, dq, tc64) * vq;
-  }
-  out0 = lane < n ? a0 : 0.0;
-  out1 = lane + 64 < n ? a1 : 0.0;
+__device__ __forceinline__ float wave_max_abs(float x) {
+  x = fabsf(x);
+  x = fmaxf(x, dpp_f<0xB1>(x));
+  x = fmaxf(x, dpp_f<0x4E>(x));
+  x = fmaxf(x, dpp_f<0x124>(x));
+  x = fmaxf(x, dpp_f<0x128>(x));
+  return fmaxf(fmaxf(lane_value(x, 0), lane_value(x, 16)), fmaxf(lane_value(x, 32), lane_value(x, 48)));
 }
 
 // One system with the FP64-corrected estimate (see kernels_mixed.hip).
+constexpr int kRowTargets = 3;   // targets whose solution rows are staged at once
 struct MixedScratch {
-  float xa[128];    // x_1
-  float xb[128];    // x_z
-  float xc[128];    // x_t (one target at a time)
-  float zr[128];    // raw data values
-  double nu[128];   // nu_w
+  float x[2 + kRowTargets][128];   // x_1, x_z, then x_t of up to kRowTargets targets
+  float zr[128];                   // raw data values
+  double nuc[128];                 // nu_w by candidate index (0 for dropped candidates)
 };
 
-struct MixedSmem {
+// FP64 tables shared by the refined kernels' blocks.
+struct MixedTables {
   double tc64[kTcSize];
   double t064[kT0Size];
   MixedScratch ms[4];
 };
 
-__device__ __forceinline__ float wave_max_abs(float x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-  return x;
+// Refined estimates: the FP64 covariance of every candidate pair, so an entry
+// of the FP64 matrix-vector product is one LDS read (the row stride is odd to
+// spread the lanes' rows over the banks).
+constexpr int kCcStride = kMaxCand | 1;
+struct MixedSmem : MixedTables {
+  double cc64[kMaxCand * kCcStride];
+  __device__ __forceinline__ const double* row(int c) const { return cc64 + c * kCcStride; }
+  __device__ __forceinline__ double at(const double* row, int cq) const { return row[cq]; }
+};
+
+// Leave-one-slice-out blocks also need the pair class (for the derivative
+// tables), so they keep a byte class table instead.
+struct LosoSmem : MixedTables {
+  uint8_t cls8[kMaxCand * kMaxCand];
+  int stride;
+  __device__ __forceinline__ const uint8_t* row(int c) const { return cls8 + c * stride; }
+  __device__ __forceinline__ double at(const uint8_t* row, int cq) const { return tc64[row[cq]]; }
+};
+
+__device__ __forceinline__ void mixed_tables(const SolveArgs& a, MixedTables& mt, double tscale) {
+  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) mt.tc64[i] = a.tab.tc_d[i] * tscale;
+  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) mt.t064[i] = a.tab.t0_d[i] * tscale;
 }
 
-template <int NB, int UPD>
+// Block set-up of the refined kernels (covariances times tscale). Needs the
+// block's candidate descriptors.
+__device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float>& sm, MixedSmem& msm,
+                                            double tscale) {
+  mixed_tables(a, msm, tscale);
+  const int nc = a.geo.ncand;
+  for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
+    const int p = i / nc, q = i - p * nc;
+    msm.cc64[p * kCcStride + q] = a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale;
+  }
+}
+__device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float>& sm, LosoSmem& msm,
+                                            double tscale) {
+  mixed_tables(a, msm, tscale);
+  const int nc = a.geo.ncand;
+  if (threadIdx.x == 0) msm.stride = nc;
+  for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
+    const int p = i / nc, q = i - p * nc;
+    msm.cls8[i] = (uint8_t)pair_class(sm.sdesc[p], sm.sdesc[q]);
+  }
+}
+
+// (C v)_p for the lane's points p = lane, lane + 64, in FP64. v is indexed by
+// candidate (zero for dropped candidates), so the loop runs over the whole
+// window with fixed offsets from each lane's row: no index loads on the way.
+template <typename MS>
+__device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, const double* vc,
+                                         const MS& ms, double& out0, double& out1) {
+  const int lane = threadIdx.x & 63;
+  const auto row0 = ms.row(lane < n ? (desc[lane] & 0x7f) : 0);
+  const auto row1 = ms.row(lane + 64 < n ? (desc[lane + 64] & 0x7f) : 0);
+  double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (; c + 4 <= ncand; c += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double vq = vc[c + u];
+      a0[u] += ms.at(row0, c + u) * vq;
+      a1[u] += ms.at(row1, c + u) * vq;
+    }
+  }
+  for (; c < ncand; ++c) {
+    const double vq = vc[c];
+    a0[0] += ms.at(row0, c) * vq;
+    a1[0] += ms.at(row1, c) * vq;
+  }
+  out0 = lane < n ? (a0[0] + a0[1]) + (a0[2] + a0[3]) : 0.0;
+  out1 = lane + 64 < n ? (a1[0] + a1[1]) + (a1[2] + a1[3]) : 0.0;
+}
+
+template <int NB, int UPD, typename MS>
 __device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& ws, const Smem<float>& sm,
-                                             MixedScratch& mx, const MixedSmem& ms, int ncand,
+                                             MixedScratch& mx, const MS& ms, int ncand,
                                              int ntgt, double sill, double* est_out,
                                              float* var_out, float& mn, float& mxp, bool& bad,
                                              double* w_out = nullptr, double* nu_scale = nullptr) {
@@ -337,48 +426,70 @@ __device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& 
     *var_out = (float)(sill * (double)(1.0f - gtt + (1.0f - g1t) * m));
   }
   __builtin_amdgcn_wave_barrier();
-  // ---- 3. explicit solutions ----
+  // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' ----
   f32x4 Z[NB];
   back_substitute<NB, UPD>(nb, Ls, Xs, ws.buf, Z);
-  write_row<NB>(Z, ne, mx.xa);
-  write_row<NB>(Z, ne + 1, mx.xb);
-  const double x1_0 = p0 < n ? (double)mx.xa[p0] : 0.0, x1_1 = p1 < n ? (double)mx.xa[p1] : 0.0;
-  const double xz_0 = p0 < n ? (double)mx.xb[p0] : 0.0, xz_1 = p1 < n ? (double)mx.xb[p1] : 0.0;
-  const double g11 = wave_sum_d(x1_0 + x1_1);
-  const double g1z = wave_sum_d(xz_0 + xz_1);
-  const double nu_mu = g1z / g11;
+  write_rows<NB>(Z, ne, 2 + (ntgt < kRowTargets ? ntgt : kRowTargets), 0, mx.x);
+  const double x1_0 = p0 < n ? (double)mx.x[0][p0] : 0.0, x1_1 = p1 < n ? (double)mx.x[0][p1] : 0.0;
+  const double xz_0 = p0 < n ? (double)mx.x[1][p0] : 0.0, xz_1 = p1 < n ? (double)mx.x[1][p1] : 0.0;
+  double s01[2] = {x1_0 + x1_1, xz_0 + xz_1};
+  wave_sums(s01);
+  const double g11 = s01[0];
+  const double nu_mu = s01[1] / g11;
   const double nu0 = xz_0 - nu_mu * x1_0, nu1 = xz_1 - nu_mu * x1_1;
-  if (p0 < n) mx.nu[p0] = nu0;
-  if (p1 < n) mx.nu[p1] = nu1;
+  mx.nuc[lane] = 0.0;
+  mx.nuc[lane + 64] = 0.0;
+  __builtin_amdgcn_wave_barrier();
+  if (p0 < n) mx.nuc[ws.desc[p0] & 0x7f] = nu0;
+  if (p1 < n) mx.nuc[ws.desc[p1] & 0x7f] = nu1;
   __builtin_amdgcn_wave_barrier();
   // ---- 4. FP64 correction ----
+  // With h = z' - C nu_w - nu_mu 1 (the FP64 residual of the adjoint system)
+  // and w_t = x_t - mu_t x_1,  z'w_t + nu'(r_t - K lambda_t) equals
+  //   A_t - mu_t B + nu_mu,  A_t = h'x_t + nu_w'c0_t,  B = h'x_1 + 1'nu_w.
   double cn0, cn1;
-  matvec64(n, ws.desc, mx.nu, ms.tc64, cn0, cn1);
-  const double sum_nu = wave_sum_d(nu0 + nu1);
+  matvec64(n, ncand, ws.desc, mx.nuc, ms, cn0, cn1);
   const double zd = (double)zref;
   const double sd = ldexp(1.0, ex);
   const double isd = ldexp(1.0, -ex);
-  const double zp0 = p0 < n ? ((double)mx.zr[p0] - zd) * isd : 0.0;
-  const double zp1 = p1 < n ? ((double)mx.zr[p1] - zd) * isd : 0.0;
+  const double h0 = p0 < n ? ((double)mx.zr[p0] - zd) * isd - cn0 - nu_mu : 0.0;
+  const double h1 = p1 < n ? ((double)mx.zr[p1] - zd) * isd - cn1 - nu_mu : 0.0;
   const int d0 = p0 < n ? ws.desc[p0] : 0, d1 = p1 < n ? ws.desc[p1] : 0;
-  for (int t = 1; t <= ntgt; ++t) {
-    write_row<NB>(Z, ne + 1 + t, mx.xc);
-    const double xc0 = p0 < n ? (double)mx.xc[p0] : 0.0, xc1 = p1 < n ? (double)mx.xc[p1] : 0.0;
-    const double g1t = wave_sum_d(xc0 + xc1);
-    const double mu = (g1t - 1.0) / g11;
-    const double w0 = xc0 - mu * x1_0, w1 = xc1 - mu * x1_1;
-    const double c00 = p0 < n ? ms.t064[(t - 1) * kT0Stride + (d0 >> 16)] : 0.0;
-    const double c01 = p1 < n ? ms.t064[(t - 1) * kT0Stride + (d1 >> 16)] : 0.0;
-    const double zw = wave_sum_d(zp0 * w0 + zp1 * w1);
-    const double s_nc = wave_sum_d(nu0 * c00 + nu1 * c01);
-    const double s_cw = wave_sum_d(cn0 * w0 + cn1 * w1);
-    const double s_w = wave_sum_d(w0 + w1);
-    const double delta = s_nc + nu_mu - s_cw - nu_mu * s_w - sum_nu * mu;
-    if (lane == t - 1) *est_out = zd + sd * (zw + delta);
-    if (w_out && t == 1) {
-      if (p0 < n) w_out[p0] = w0;
-      if (p1 < n) w_out[p1] = w1;
+  double B = 0.0;
+  for (int t0 = 1; t0 <= ntgt; t0 += kRowTargets) {
+    const int cnt = (ntgt - t0 + 1) < kRowTargets ? (ntgt - t0 + 1) : kRowTargets;
+    if (t0 > 1) write_rows<NB>(Z, ne + 1 + t0, cnt, 2, mx.x);
+    double s[2 * kRowTargets + 1];
+#pragma unroll
+    for (int k = 0; k < kRowTargets; ++k) {
+      s[2 * k] = 0.0;
+      s[2 * k + 1] = 0.0;
+      if (k < cnt) {
+        const int t = t0 + k;
+        const double xt0 = p0 < n ? (double)mx.x[2 + k][p0] : 0.0;
+        const double xt1 = p1 < n ? (double)mx.x[2 + k][p1] : 0.0;
+        const double c00 = p0 < n ? ms.t064[(t - 1) * kT0Stride + (d0 >> 16)] : 0.0;
+        const double c01 = p1 < n ? ms.t064[(t - 1) * kT0Stride + (d1 >> 16)] : 0.0;
+        s[2 * k] = xt0 + xt1;
+        s[2 * k + 1] = (h0 * xt0 + h1 * xt1) + (nu0 * c00 + nu1 * c01);
+      }
     }
+    s[2 * kRowTargets] = t0 == 1 ? (h0 * x1_0 + h1 * x1_1) + (nu0 + nu1) : 0.0;
+    wave_sums(s);
+    if (t0 == 1) B = s[2 * kRowTargets];
+#pragma unroll
+    for (int k = 0; k < kRowTargets; ++k) {
+      if (k < cnt) {
+        const int t = t0 + k;
+        const double mu = (s[2 * k] - 1.0) / g11;
+        if (lane == t - 1) *est_out = zd + sd * (s[2 * k + 1] - mu * B + nu_mu);
+        if (w_out && t == 1) {
+          if (p0 < n) w_out[p0] = (double)mx.x[2][p0] - mu * x1_0;
+          if (p1 < n) w_out[p1] = (double)mx.x[2][p1] - mu * x1_1;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   if (nu_scale) *nu_scale = sd;
   __builtin_amdgcn_wave_barrier();
