@@ -60,9 +60,15 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long x) {
 constexpr int tix(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // 1/sqrt(x): the hardware reciprocal square root in FP32 (about 1 ulp, well
-// inside the FP32 factorisation error), the correctly rounded form in FP64.
+// inside the FP32 factorisation error). In FP64 the hardware estimate (relative
+// error about 5e-8) takes one second-order Newton step in residual form,
+// y = y0 + y0 e (1/2 + 3e/8) with e = 1 - x y0^2, which leaves about 1.3 ulp.
 __device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ double inv_sqrt(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y0, y0, 1.0);
+  return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
 
 // Tile column held by element v of lane group g (see the layout note above).
 template <typename T> __device__ __forceinline__ constexpr int colmap(int g, int v);
@@ -226,11 +232,12 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
 }
 
 // FP64 layout: the panel's columns 4p+k sit in element p of lane group k, which
-// is already the MFMA operand layout; the in-panel updates take each column
-// from its lane group with a cross-lane shuffle.
+// is already the MFMA operand layout. The panel (and the same columns of X) is
+// copied through LDS so that every lane group holds all four columns of its
+// row; the in-panel elimination then runs lane-locally (redundantly in the
+// four groups) and each group takes its own column back.
 __device__ __forceinline__ void diag_factor(f64x4& D, f64x4& X, int ne, double* buf, double& minpiv,
                                             double& maxpiv, bool& bad) {
-  (void)buf;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -238,37 +245,41 @@ __device__ __forceinline__ void diag_factor(f64x4& D, f64x4& X, int ne, double* 
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     if (4 * p < ne) {
-      double u = 0.0;
+      buf[r * 8 + g] = D[p];
+      buf[r * 8 + 4 + g] = X[p];
+      __builtin_amdgcn_wave_barrier();
+      double dl[4], xl[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        dl[k] = buf[r * 8 + k];
+        xl[k] = buf[r * 8 + 4 + k];
+      }
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int k0 = 0; k0 < 4; ++k0) {
         const int c = 4 * p + k0;
         if (c < ne) {
-          const bool mine = (g == k0);
-          const double piv = take_pivot(-lane_value(D[p], 16 * k0 + c), minpiv, maxpiv, bad);
+          const double piv = take_pivot(-lane_value(dl[k0], c), minpiv, maxpiv, bad);
           const double is = inv_sqrt(piv);
-          const double l = (r > c) ? -D[p] * is : 0.0;   // L[r][c] in lane group k0
-          X[p] = mine ? X[p] * is : X[p];
-          u = mine ? l : u;
-          if (k0 < 3) {
-            const double lb = __shfl(l, 16 * k0 + r, 64);
-            const double xb = __shfl(X[p], 16 * k0 + r, 64);
-            double s = 0.0;   // L[4p+g][c] for the later columns of the panel
+          const double l = (r > c) ? -dl[k0] * is : 0.0;   // L[r][c]
+          dl[k0] = l;
+          xl[k0] *= is;
 #pragma unroll
-            for (int k1 = k0 + 1; k1 < 4; ++k1) {
-              const double sk = lane_value(l, 16 * k0 + 4 * p + k1);
-              s = (g == k1) ? sk : s;
-            }
-            const bool later = g > k0;
-            D[p] = later ? D[p] + lb * s : D[p];
-            X[p] = later ? X[p] - xb * s : X[p];
+          for (int k1 = k0 + 1; k1 < 4; ++k1) {
+            const double s = lane_value(l, 4 * p + k1);   // L[c1][c]
+            dl[k1] += l * s;
+            xl[k1] -= xl[k0] * s;
           }
         }
       }
+      const double dg = g == 0 ? dl[0] : (g == 1 ? dl[1] : (g == 2 ? dl[2] : dl[3]));
+      const double xg = g == 0 ? xl[0] : (g == 1 ? xl[1] : (g == 2 ? xl[2] : xl[3]));
+      D[p] = dg;
+      X[p] = xg;
       if (p < 3) {
-        const double ut = (r >= 4 * p + 4) ? u : 0.0;
-        const double xw = X[p];
-        D = mfma4(ut, ut, D);
-        X = mfma4(-ut, xw, X);
+        const double u = (4 * p + g < ne && r >= 4 * p + 4) ? dg : 0.0;
+        D = mfma4(u, u, D);
+        X = mfma4(-u, xg, X);
       }
     }
   }
