@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_160x512")
     ap.add_argument("--precision", default="mixed_fp16")
+    ap.add_argument("--refine-max", type=int, default=1,
+                    help="mixed precisions: 0 = factorisation read-out only, 1 = FP64 correction")
+    ap.add_argument("--refine-tol", type=float, default=0.0,
+                    help="refinement / routing threshold (okr_problem.refine_tol)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -125,7 +129,8 @@ def main():
     dev = torch.device("cuda:0")
     st = torch.from_numpy(s).to(dev)
     et = torch.from_numpy(e).to(dev) if e is not None else None
-    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched")
+    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
+                  refine_max=args.refine_max, refine_tol=args.refine_tol)
     vol = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
     var = torch.empty_like(vol)
     for _ in range(args.warmup):
@@ -285,6 +290,9 @@ def main():
         "loso": loso,
         "calibration": calib,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in stats["phase_ms"].items()},
+        "solver_stats": {k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
+                                               "n_nonpositive_pivot", "n_not_converged",
+                                               "max_kappa_est")},
         "host_wall_s": round(t_host, 3),
     }
     print(json.dumps(out))

@@ -95,10 +95,24 @@ typedef struct {
   int32_t min_points;   /* neighbour floor, 1..2*(2r+1)^2; 4 is the usual value */
   int32_t precision;    /* okr_precision */
   int32_t algo;         /* okr_algo */
-  double  refine_tol;   /* MIXED_*: condition-estimate x unit roundoff above
-                           which the FP64-residual correction runs (e.g. 1e-4) */
-  int32_t refine_max;   /* MIXED_*: correction steps, 0..4 */
-  int32_t strict;       /* 1: OKR_E_NOT_CONVERGED is returned at the next sync */
+  double  refine_tol;   /* >= 0. With kappa the system's pivot-ratio condition
+                           estimate and u = 2^-24:
+                           MIXED_* with refine_max >= 1 run the FP64 correction
+                           on systems with kappa*u > refine_tol (0: on every
+                           system);
+                           MIXED_* with refine_max = 0 re-solve in FP64 the
+                           systems whose error indicator
+                           kappa*u*s / max(|z_hat|, 0.01*max|known voxel|)
+                           exceeds refine_tol for some target (s: the power of
+                           two above the spread of the system's data; 0: none);
+                           FP32 re-solves systems with kappa*u > refine_tol in
+                           FP64 (0: never). Ignored by FP64. */
+  int32_t refine_max;   /* MIXED_*, 0..4: 0 = no correction (the low-precision
+                           factorisation's own read-out); >= 1 = the correction,
+                           taken once (it squares the relative error of the
+                           factorisation, so one step reaches the FP64 result) */
+  int32_t strict;       /* 1: OKR_E_NOT_CONVERGED is returned at the next sync if a
+                           system met a non-positive pivot in its FP64 re-solve */
 } okr_problem;
 
 typedef struct okr_plan okr_plan;   /* opaque: workspace, tables, launch state */
@@ -117,6 +131,7 @@ typedef struct {
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
                                  6 plain per-voxel kernel, 7 leave-one-slice-out */
   int64_t phase_calls[8];     /* launches timed per phase */
+  int64_t n_not_converged;    /* systems whose FP64 re-solve also met a non-positive pivot */
 } okr_stats;
 
 #define OKR_PHASE_PLACE 0
@@ -141,7 +156,8 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
  *   d_variance float32, same shape as d_volume; NULL = not written
  *   d_flags    uint8 [(nslices-1)][ny][nx] per (column, gap) system; NULL =
  *              not written. Bits: 1 floor-filled, 2 FP64-residual correction,
- *              4 FP64 re-solve, 8 non-positive pivot in the first pass.
+ *              4 FP64 re-solve, 8 non-positive pivot in the first pass,
+ *              16 non-positive pivot in the FP64 re-solve as well.
  * Input and output buffers must not overlap. */
 okr_status okr_execute(okr_plan* plan, const okr_variogram* vario,
                        const float* d_slices, const uint8_t* d_edge,
@@ -178,6 +194,32 @@ okr_status okr_plan_destroy(okr_plan* plan);
  * plan's stream and okr_stats_get reports the summed device time per phase
  * (then clears it). Off by default; costs one event pair per phase. */
 okr_status okr_plan_set_profiling(okr_plan* plan, int32_t enable);
+
+/* Launch graph: when enabled, okr_execute records its launch sequence into a
+ * HIP graph (captured on a private stream of the plan) the first time it is
+ * called with a given variogram, buffer set and tuning, and afterwards
+ * replays that graph on the plan's stream; a call with other arguments
+ * re-captures. Results are those of the direct launches. With profiling on,
+ * one mark (phase 4) spans the whole replay. Off by default. */
+okr_status okr_plan_set_graph(okr_plan* plan, int32_t enable);
+
+/* Autotuner: times the plan's own okr_execute on the given inputs (buffers as
+ * in okr_execute; flags are not written) for each candidate launch shape --
+ * 1 to 4 persistent workgroups per compute unit and, for MIXED_*, the split
+ * low-precision or the FP32 trailing-update arithmetic (the FP32 form is at
+ * least as accurate) -- and keeps the fastest for later calls. Synchronises
+ * the plan's stream. Every candidate computes the same problem; the last one
+ * timed leaves its result in d_volume / d_variance. */
+okr_status okr_plan_autotune(okr_plan* plan, const okr_variogram* vario, const float* d_slices,
+                             const uint8_t* d_edge, float* d_volume, float* d_variance);
+
+/* The plan's launch shape: workgroups per compute unit, mixed update
+ * arithmetic (-1: the precision's own, 0: FP32, 1: split FP16, 2: split BF16)
+ * and, after okr_plan_autotune, the time of each candidate in ms (double[8],
+ * nullable; candidates in the order grid 1..4, each with the precision's own
+ * then FP32 updates for MIXED_*, grid 1..4 otherwise). */
+okr_status okr_plan_get_tuning(const okr_plan* plan, int32_t* grid_per_cu, int32_t* update_arith,
+                               double* cand_ms);
 
 const char* okr_status_string(okr_status status);
 const char* okr_plan_last_error(const okr_plan* plan);

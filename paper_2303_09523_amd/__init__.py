@@ -45,7 +45,7 @@ class Plan:
 
     def __init__(self, nx: int, ny: int, nslices: int, upsample: int, radius: int,
                  min_points: int = 4, precision: str = "fp32", algo: str = "batched",
-                 refine_tol: float = 1e-4, refine_max: int = 1, strict: bool = False,
+                 refine_tol: float = 0.0, refine_max: int = 1, strict: bool = False,
                  stream=None):
         torch = _torch()
         lib = load()
@@ -107,6 +107,30 @@ class Plan:
                                       _ptr(volume), _ptr(variance), _ptr(flags)), self._h)
         return volume, variance, flags
 
+    def set_graph(self, enable: bool = True):
+        """Replay okr_execute from a captured HIP graph (see okr_plan_set_graph)."""
+        _lib.check(load().okr_plan_set_graph(self._h, int(bool(enable))), self._h)
+
+    def autotune(self, slices, vario, edge=None, volume=None, variance=None) -> dict:
+        """Pick the fastest launch shape on these inputs (okr_plan_autotune)."""
+        torch = _torch()
+        self._check_in(slices, torch.float32, self.shape, "slices")
+        if edge is not None:
+            self._check_in(edge, torch.uint8, self.shape, "edge")
+        dev = slices.device
+        if volume is None:
+            volume = torch.empty(self.out_shape(), dtype=torch.float32, device=dev)
+        v = _as_vario(vario)
+        _lib.check(load().okr_plan_autotune(self._h, C.byref(v), _ptr(slices), _ptr(edge),
+                                            _ptr(volume), _ptr(variance)), self._h)
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        g, u = C.c_int32(), C.c_int32()
+        ms = (C.c_double * 8)()
+        _lib.check(load().okr_plan_get_tuning(self._h, C.byref(g), C.byref(u), ms), self._h)
+        return {"grid_per_cu": g.value, "update_arith": u.value, "candidate_ms": list(ms)}
+
     def select(self, edge=None):
         """Kept-candidate bitmasks [(n-1)*ny*nx][2] (int64 view of uint64) and counts."""
         torch = _torch()
@@ -143,6 +167,7 @@ class Plan:
                 "n_floor_filled": s.n_floor_filled, "n_refined": s.n_refined,
                 "n_fp64_fallback": s.n_fp64_fallback,
                 "n_nonpositive_pivot": s.n_nonpositive_pivot, "max_kappa_est": s.max_kappa_est,
+                "n_not_converged": s.n_not_converged,
                 "phase_ms": dict(zip(_lib.PHASES, list(s.phase_ms))),
                 "phase_calls": dict(zip(_lib.PHASES, list(s.phase_calls)))}
 

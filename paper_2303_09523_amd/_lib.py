@@ -22,7 +22,8 @@ ALGOS = {"batched": 0, "plain": 1}
 
 EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
-            "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling"]
+            "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling",
+            "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning"]
 
 
 class Variogram(C.Structure):
@@ -42,7 +43,7 @@ class Stats(C.Structure):
                 ("n_floor_filled", C.c_int64), ("n_refined", C.c_int64),
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
                 ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 8),
-                ("phase_calls", C.c_int64 * 8)]
+                ("phase_calls", C.c_int64 * 8), ("n_not_converged", C.c_int64)]
 
 
 class OkrError(RuntimeError):
@@ -77,6 +78,9 @@ def load():
         "okr_version": (C.c_int32, []),
         "okr_abi_sizes": (C.c_int32, [P(C.c_int64)]),
         "okr_plan_set_profiling": (C.c_int32, [VP, C.c_int32]),
+        "okr_plan_set_graph": (C.c_int32, [VP, C.c_int32]),
+        "okr_plan_autotune": (C.c_int32, [VP, P(Variogram), VP, VP, VP, VP]),
+        "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
       double est = 0.0, zscale = 1.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      mixed_system<NB, 0, LosoSmem>(n, nb, ws, sm, mx, msm, ncand, 1, a.sill, &est, &var, mn, mxp, bad,
+      mixed_system<NB, 0, true, LosoSmem>(n, nb, ws, sm, mx, msm, ncand, 1, a.sill, 0.0, &est, &var, mn, mxp, bad,
                           BACKWARD ? wv : nullptr, &zscale);
       est = __shfl(est, 0, 64);
       const unsigned gap = sys / plane;

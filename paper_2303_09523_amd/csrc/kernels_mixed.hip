@@ -18,8 +18,11 @@
 //        z_hat_t = z' w_t + nu' r_t - (K nu)' lambda_t
 //      which is exact up to the product of the errors of nu and lambda_t, so
 //      the estimate reaches FP64-level accuracy from a low-precision factor.
-//      The one FP64 matrix-vector product C nu_w per system uses the FP64
-//      pair-class covariance table.
+//      The one FP64 matrix-vector product C nu_w per system uses a per-block
+//      FP64 table of every candidate pair's covariance.
+// Steps 3-4 run when the correction is enabled (a launch-time choice) and the
+// system's pivot-ratio condition estimate exceeds a threshold; otherwise the
+// estimate is the Schur read-out of step 2 in the normalised units.
 // The kriging variance comes from the factorisation's Schur block (FP32).
 // Systems with a non-positive pivot are queued for the FP64 re-solve.
 #include "solver_refine.h"
@@ -27,8 +30,13 @@
 namespace okr {
 namespace {
 
-template <int NB, int UPD>
-__global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
+constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;   // 2^-24
+
+// Without the correction the kernel holds only the factorisation's live tiles
+// and is compiled for two waves per SIMD, like the FP32 kernel.
+template <int NB, int UPD, bool CORR>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CORR ? 1 : 2)))
+void mixed_class_kernel(SolveArgs a) {
   __shared__ Smem<float> sm;
   __shared__ MixedSmem msm;
   const double tscale = 1.0 / a.sill;
@@ -47,6 +55,7 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
   unsigned long long* cursor = &a.ctr->cls_next[NB];
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
+  const double zfloor = 0.01 * (double)__uint_as_float(a.ctr->zmax_bits);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int d0 = sm.sdesc[lane];
   const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
@@ -71,22 +80,35 @@ __global__ __launch_bounds__(256) void mixed_class_kernel(SolveArgs a) {
       double est = 0.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      mixed_system<NB, UPD>(n, nb, ws, sm, mx, msm, ncand, ntgt, a.sill, &est, &var, mn, mxp, bad);
-      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally);
-      if (lane == 0 && a.flags && !bad) a.flags[sys] |= kFlagRefined;
-      refined += bad ? 0 : 1;
+      double scale = 1.0;
+      const bool corr = mixed_system<NB, UPD, CORR>(n, nb, ws, sm, mx, msm, ncand, ntgt, a.sill,
+                                                    a.refine_kappa, &est, &var, mn, mxp, bad,
+                                                    nullptr, &scale);
+      bool route = false;
+      if (!CORR && a.route_tol > 0.0) {
+        // error indicator of the read-out per target: kappa u s / max(|z_hat|, 0.01 Zmax)
+        // (kappa: pivot-ratio estimate, s: the power of two bounding the data spread)
+        const double den = fmax(fabs(est), zfloor);
+        const double ind = (lane < ntgt && den > 0.0)
+                               ? ((double)mxp / (double)mn) * kUnitRoundoff32 * scale / den
+                               : 0.0;
+        route = __any(ind > a.route_tol);
+      }
+      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally, route);
+      if (lane == 0 && a.flags && corr && !bad) a.flags[sys] |= kFlagRefined;
+      refined += (corr && !bad) ? 1 : 0;
     }
   }
   flush_tally(a, tally);
   if (lane == 0 && refined) atomicAdd(&a.ctr->refined, refined);
 }
 
-template <int UPD>
+template <int UPD, bool CORR>
 hipError_t launch_mixed_classes(const SolveArgs& a, int grid, hipStream_t s) {
   const int nbmax = (a.geo.ncand + a.nb + 15) / 16;
 #define OKR_CLS(K)                                                                            \
   if (nbmax >= K) {                                                                           \
-    hipLaunchKernelGGL((mixed_class_kernel<K, UPD>), dim3(grid), dim3(256), 0, s, a);         \
+    hipLaunchKernelGGL((mixed_class_kernel<K, UPD, CORR>), dim3(grid), dim3(256), 0, s, a);   \
     hipError_t e = hipGetLastError();                                                         \
     if (e != hipSuccess) return e;                                                            \
   }
@@ -98,8 +120,11 @@ hipError_t launch_mixed_classes(const SolveArgs& a, int grid, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s) {
-  if (a.precision == 2) return launch_mixed_classes<2>(a, grid, s);
-  return launch_mixed_classes<1>(a, grid, s);
+  if (a.upd == 2)
+    return a.refine ? launch_mixed_classes<2, true>(a, grid, s) : launch_mixed_classes<2, false>(a, grid, s);
+  if (a.upd == 0)
+    return a.refine ? launch_mixed_classes<0, true>(a, grid, s) : launch_mixed_classes<0, false>(a, grid, s);
+  return a.refine ? launch_mixed_classes<1, true>(a, grid, s) : launch_mixed_classes<1, false>(a, grid, s);
 }
 
 }  // namespace okr

@@ -94,7 +94,9 @@ __global__ void reset_kernel(DevCounters* c) {
     c->refined = 0;
     c->fp64_fallback = 0;
     c->bad_pivot = 0;
+    c->failed = 0;
     c->max_kappa_bits = 0;
+    c->zmax_bits = 0;
     c->nonfinite = 0;
     c->offsets[kHist] = 0;
     c->n_fallback_list = 0;
@@ -111,22 +113,28 @@ __global__ void reset_cursors_kernel(DevCounters* c) {
 }
 
 // Known slice s -> plane s*f of the volume; variance 0 there. Also latches
-// non-finite inputs.
+// non-finite inputs and records the largest |known voxel| (the floor of the
+// per-voxel error measure of the mixed path's routing).
 __global__ void place_kernel(const float* __restrict__ slices, float* __restrict__ volume,
                              float* __restrict__ variance, long long plane, int nslices, int f,
                              DevCounters* ctr) {
   long long total = plane * nslices;
   bool bad = false;
+  float amax = 0.0f;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     long long s = i / plane, p = i - s * plane;
     float v = slices[i];
     bad |= !isfinite(v);
+    if (isfinite(v)) amax = fmaxf(amax, fabsf(v));
     long long o = s * f * plane + p;
     volume[o] = v;
     if (variance) variance[o] = 0.0f;
   }
   if (bad) atomicOr(&ctr->nonfinite, 1u);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if ((threadIdx.x & 63) == 0 && amax > 0.0f) atomicMax(&ctr->zmax_bits, __float_as_uint(amax));
 }
 
 constexpr int kSelTile = 16;

@@ -46,6 +46,28 @@ struct okr_plan {
   const uint8_t* loso_edge = nullptr;
   long long last_nsys = 0, last_kriged = 0;
   bool profiling = false;
+  bool timers_off = false;      // no profiling marks while a graph is captured
+  int grid_per_cu = 3;          // persistent workgroups per compute unit (autotuned)
+  int upd = -1;                 // mixed trailing-update arithmetic (-1: from the precision)
+  bool tuned = false;
+  double tune_ms[8] = {0};      // autotune: best time per candidate, ms
+  // launch graph of okr_execute, keyed by its arguments
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    okr_variogram v;
+    const float* slices;
+    const uint8_t* edge;
+    float* volume;
+    float* variance;
+    uint8_t* flags;
+    bool forced;
+    int grid_per_cu, upd;
+  } gkey{};
+  bool gkey_valid = false;
+  long long graph_launches = 0, graph_captures = 0;
   struct Mark { int phase; hipEvent_t a, b; };
   std::vector<Mark> marks;
   double phase_ms[8] = {0};
@@ -172,9 +194,19 @@ okr_status dev_alloc(okr_plan* p, T** ptr, size_t count) {
 
 void drain_marks(okr_plan* p);
 
+void drop_graph(okr_plan* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  p->gkey_valid = false;
+}
+
 void free_plan(okr_plan* p) {
   if (!p) return;
   drain_marks(p);
+  drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   hipFree(p->bits);
   hipFree(p->count);
   hipFree(p->perm);
@@ -220,6 +252,10 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.nb = p->geo.f + 1;
   a.precision = p->prob.precision;
   a.kappa_limit = 1e300;
+  a.refine_kappa = 0.0;
+  a.refine = 0;
+  a.route_tol = 0.0;
+  a.upd = 1;
   a.fallback = nullptr;
   a.step = 1;
   a.resid = nullptr;
@@ -228,7 +264,9 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   return a;
 }
 
-int persistent_grid(okr_plan* p) { return p->num_cu * 3; }
+int persistent_grid(okr_plan* p) { return p->num_cu * p->grid_per_cu; }
+
+constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;   // 2^-24
 
 // Brackets one phase's launches with events when profiling is on.
 struct PhaseTimer {
@@ -236,7 +274,7 @@ struct PhaseTimer {
   int phase;
   hipEvent_t a = nullptr, b = nullptr;
   PhaseTimer(okr_plan* plan, int ph) : p(plan), phase(ph) {
-    if (!p->profiling) return;
+    if (!p->profiling || p->timers_off) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
       (void)hipGetLastError();
       a = b = nullptr;
@@ -355,6 +393,142 @@ okr_status okr_plan_destroy(okr_plan* p) {
   return OKR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+bool force_fallback() {
+  const char* force = std::getenv("OKR_FORCE_FALLBACK");
+  return force && force[0] == '1';
+}
+
+// The launch sequence of okr_execute on stream `strm` (the plan's stream, or
+// the capture stream of its graph).
+okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* vario,
+                           const float* d_slices, const uint8_t* d_edge, float* d_volume,
+                           float* d_variance, uint8_t* d_flags) {
+  const okr::Geometry& g = p->geo;
+  OKR_HIP(p, okr::launch_reset(p->ctr, strm));
+  {
+    PhaseTimer t(p, OKR_PHASE_PLACE);
+    OKR_HIP(p, okr::launch_place(d_slices, d_volume, d_variance, g, p->ctr, strm));
+  }
+  if (g.nslices < 2 || g.f < 2) return OKR_OK;
+  {
+    PhaseTimer t(p, OKR_PHASE_TABLES);
+    OKR_HIP(p, okr::launch_tables(vario_of(vario), g, tables_of(p), strm));
+  }
+  if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL) {
+    PhaseTimer t(p, OKR_PHASE_PLAIN);
+    OKR_HIP(p, okr::launch_plain(d_slices, d_edge, d_volume, d_variance, g, p->rule,
+                                 vario_of(vario), strm));
+    return OKR_OK;
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_SELECT);
+    OKR_HIP(p, okr::launch_select(d_edge, g, p->rule, p->bits, p->count, p->ctr, strm));
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_BUCKET);
+    OKR_HIP(p, okr::launch_bucket(p->count, g, p->perm, p->ctr, strm));
+  }
+  okr::SolveArgs a = solve_args(p, vario);
+  a.slices = d_slices;
+  a.volume = d_volume;
+  a.variance = d_variance;
+  a.flags = d_flags;
+  const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
+  // condition estimate x FP32 unit roundoff above refine_tol: FP32 systems go
+  // to the FP64 re-solve, mixed systems take the FP64 correction; without the
+  // correction, mixed systems whose error indicator exceeds refine_tol go to
+  // the FP64 re-solve
+  const double kappa_tol = p->prob.refine_tol / kUnitRoundoff32;
+  if (mixed) {
+    a.fallback = p->fallback;   // systems with a non-positive pivot
+    a.refine = p->prob.refine_max > 0 ? 1 : 0;
+    a.refine_kappa = kappa_tol;
+    if (!a.refine) a.route_tol = p->prob.refine_tol;
+    a.upd = p->upd >= 0 ? p->upd : (p->prob.precision == OKR_MIXED_BF16 ? 2 : 1);
+  } else if (p->prob.precision == OKR_FP32 && p->prob.refine_tol > 0.0) {
+    a.fallback = p->fallback;
+    a.kappa_limit = kappa_tol;
+  }
+  if (force_fallback() && p->prob.precision != OKR_FP64) {
+    a.kappa_limit = 0.0;
+    a.fallback = p->fallback;
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_SOLVE);
+    if (mixed)
+      OKR_HIP(p, okr::launch_solve_mixed(a, persistent_grid(p), strm));
+    else
+      OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), strm));
+  }
+  if (a.fallback) {
+    PhaseTimer t(p, OKR_PHASE_FALLBACK);
+    OKR_HIP(p, okr::launch_solve_fallback(a, persistent_grid(p), strm));
+  }
+  return OKR_OK;
+}
+
+bool same_key(const okr_plan::GraphKey& k, const okr_plan::GraphKey& q) {
+  return k.v.model == q.v.model && k.v.nugget == q.v.nugget && k.v.sill == q.v.sill &&
+         k.v.range == q.v.range && k.slices == q.slices && k.edge == q.edge &&
+         k.volume == q.volume && k.variance == q.variance && k.flags == q.flags &&
+         k.forced == q.forced && k.grid_per_cu == q.grid_per_cu && k.upd == q.upd;
+}
+
+// Capture the launch sequence into a graph (on the plan's private stream) if
+// the arguments differ from the captured ones, then launch it on the plan's
+// stream.
+okr_status execute_graph(okr_plan* p, const okr_variogram* vario, const float* d_slices,
+                         const uint8_t* d_edge, float* d_volume, float* d_variance,
+                         uint8_t* d_flags) {
+  okr_plan::GraphKey key{};
+  key.v = *vario;
+  key.slices = d_slices;
+  key.edge = d_edge;
+  key.volume = d_volume;
+  key.variance = d_variance;
+  key.flags = d_flags;
+  key.forced = force_fallback();
+  key.grid_per_cu = p->grid_per_cu;
+  key.upd = p->upd;
+  if (!p->gkey_valid || !same_key(p->gkey, key)) {
+    drop_graph(p);
+    if (!p->cap_stream) OKR_HIP(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    OKR_HIP(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    p->timers_off = true;
+    okr_status st =
+        enqueue_execute(p, p->cap_stream, vario, d_slices, d_edge, d_volume, d_variance, d_flags);
+    p->timers_off = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (st != OKR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(p, OKR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    p->graph = graph;
+    e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(p);
+      return fail(p, OKR_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    p->gkey = key;
+    p->gkey_valid = true;
+    p->graph_captures += 1;
+  }
+  PhaseTimer t(p, OKR_PHASE_SOLVE);
+  OKR_HIP(p, hipGraphLaunch(p->graph_exec, p->stream));
+  p->graph_launches += 1;
+  return OKR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 okr_status okr_execute(okr_plan* p, const okr_variogram* vario, const float* d_slices,
                        const uint8_t* d_edge, float* d_volume, float* d_variance,
                        uint8_t* d_flags) {
@@ -365,56 +539,88 @@ okr_status okr_execute(okr_plan* p, const okr_variogram* vario, const float* d_s
   if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
   const okr::Geometry& g = p->geo;
   p->loso_ready = false;
-  OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
-  {
-    PhaseTimer t(p, OKR_PHASE_PLACE);
-    OKR_HIP(p, okr::launch_place(d_slices, d_volume, d_variance, g, p->ctr, p->stream));
-  }
   p->last_nsys = g.nsys;
   p->last_kriged = g.nsys * (g.f - 1);
-  if (g.nslices < 2 || g.f < 2) return OKR_OK;
-  {
-    PhaseTimer t(p, OKR_PHASE_TABLES);
-    OKR_HIP(p, okr::launch_tables(vario_of(vario), g, tables_of(p), p->stream));
-  }
-  if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL) {
-    PhaseTimer t(p, OKR_PHASE_PLAIN);
-    OKR_HIP(p, okr::launch_plain(d_slices, d_edge, d_volume, d_variance, g, p->rule,
-                                 vario_of(vario), p->stream));
+  if (p->use_graph)
+    return execute_graph(p, vario, d_slices, d_edge, d_volume, d_variance, d_flags);
+  return enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, d_flags);
+}
+
+okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const float* d_slices,
+                             const uint8_t* d_edge, float* d_volume, float* d_variance) {
+  if (!p) return OKR_E_INVALID_ARG;
+  std::string msg;
+  okr_status st = validate_vario(vario, &msg);
+  if (st != OKR_OK) return fail(p, st, msg);
+  if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
+  if (p->prob.algo != OKR_ALGO_BATCHED || p->geo.nslices < 2 || p->geo.f < 2) {
+    p->tuned = true;
     return OKR_OK;
   }
-  {
-    PhaseTimer t(p, OKR_PHASE_SELECT);
-    OKR_HIP(p, okr::launch_select(d_edge, g, p->rule, p->bits, p->count, p->ctr, p->stream));
-  }
-  {
-    PhaseTimer t(p, OKR_PHASE_BUCKET);
-    OKR_HIP(p, okr::launch_bucket(p->count, g, p->perm, p->ctr, p->stream));
-  }
-  okr::SolveArgs a = solve_args(p, vario);
-  a.slices = d_slices;
-  a.volume = d_volume;
-  a.variance = d_variance;
-  a.flags = d_flags;
-  const char* force = std::getenv("OKR_FORCE_FALLBACK");
-  const bool forced = force && force[0] == '1';
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
-  if (mixed) a.fallback = p->fallback;   // systems with a non-positive pivot
-  if (forced && p->prob.precision != OKR_FP64) {
-    a.kappa_limit = 0.0;
-    a.fallback = p->fallback;
+  const int own_upd = p->prob.precision == OKR_MIXED_BF16 ? 2 : 1;
+  struct Cand { int grid, upd; };
+  std::vector<Cand> cands;
+  for (int gpc = 1; gpc <= 4; ++gpc) {
+    cands.push_back({gpc, mixed ? own_upd : -1});
+    if (mixed) cands.push_back({gpc, 0});   // FP32 updates are at least as accurate
   }
-  {
-    PhaseTimer t(p, OKR_PHASE_SOLVE);
-    if (mixed)
-      OKR_HIP(p, okr::launch_solve_mixed(a, persistent_grid(p), p->stream));
-    else
-      OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), p->stream));
+  const bool graph = p->use_graph, prof = p->profiling;
+  p->use_graph = false;
+  p->profiling = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  OKR_HIP(p, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(p, OKR_E_DEVICE, "hipEventCreate failed");
   }
-  if (a.fallback) {
-    PhaseTimer t(p, OKR_PHASE_FALLBACK);
-    OKR_HIP(p, okr::launch_solve_fallback(a, persistent_grid(p), p->stream));
+  double best = 1e300;
+  Cand pick = {p->grid_per_cu, p->upd};
+  for (size_t i = 0; i < cands.size() && st == OKR_OK; ++i) {
+    p->grid_per_cu = cands[i].grid;
+    p->upd = cands[i].upd;
+    st = enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, nullptr);
+    if (st != OKR_OK) break;
+    (void)hipEventRecord(e0, p->stream);
+    st = enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, nullptr);
+    (void)hipEventRecord(e1, p->stream);
+    if (st != OKR_OK) break;
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(p, OKR_E_DEVICE, "autotune timing failed");
+      break;
+    }
+    if (i < 8) p->tune_ms[i] = ms;
+    if (ms < best) {
+      best = ms;
+      pick = cands[i];
+    }
   }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->grid_per_cu = pick.grid;
+  p->upd = pick.upd;
+  p->use_graph = graph;
+  p->profiling = prof;
+  if (st == OKR_OK) p->tuned = true;
+  drop_graph(p);
+  return st;
+}
+
+okr_status okr_plan_get_tuning(const okr_plan* p, int32_t* grid_per_cu, int32_t* update_arith,
+                               double* cand_ms) {
+  if (!p) return OKR_E_INVALID_ARG;
+  if (grid_per_cu) *grid_per_cu = p->grid_per_cu;
+  if (update_arith) *update_arith = p->upd;
+  if (cand_ms)
+    for (int i = 0; i < 8; ++i) cand_ms[i] = p->tune_ms[i];
+  return OKR_OK;
+}
+
+okr_status okr_plan_set_graph(okr_plan* p, int32_t enable) {
+  if (!p) return OKR_E_INVALID_ARG;
+  p->use_graph = enable != 0;
+  if (!p->use_graph) drop_graph(p);
   return OKR_OK;
 }
 
@@ -528,7 +734,10 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
     p->phase_ms[i] = 0.0;
     p->phase_calls[i] = 0;
   }
+  out->n_not_converged = (int64_t)c.failed;
   if (c.nonfinite) return fail(p, OKR_E_NONFINITE, "a known voxel is not finite");
+  if (p->prob.strict && c.failed)
+    return fail(p, OKR_E_NOT_CONVERGED, "a system met a non-positive pivot in FP64 as well");
   return OKR_OK;
 }
 

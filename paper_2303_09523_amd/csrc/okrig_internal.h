@@ -20,7 +20,8 @@ constexpr int kHist = 128;                         // histogram bins over n
 constexpr uint8_t kFloorBit = 0x80;
 
 // Flag bits written per system (see okrig.h).
-constexpr uint8_t kFlagFloor = 1, kFlagRefined = 2, kFlagFp64 = 4, kFlagBadPivot = 8;
+constexpr uint8_t kFlagFloor = 1, kFlagRefined = 2, kFlagFp64 = 4, kFlagBadPivot = 8,
+                  kFlagFailed = 16;
 
 struct Geometry {
   int nx, ny, nslices, f, r, W, W2, ncand, min_points;
@@ -54,7 +55,9 @@ struct DevCounters {
   unsigned long long refined;
   unsigned long long fp64_fallback;
   unsigned long long bad_pivot;
+  unsigned long long failed;        // systems whose FP64 re-solve also met a bad pivot
   unsigned int max_kappa_bits;      // float bits of the largest estimate
+  unsigned int zmax_bits;           // float bits of the largest |known voxel|
   unsigned int nonfinite;           // nonzero if a known voxel is not finite
   unsigned long long offsets[kHist + 1];  // bucket starts (largest n first)
   unsigned long long cursor[kHist];
@@ -90,6 +93,10 @@ struct SolveArgs {
   int nb;               // border rows: f + 1
   int precision;        // okr_precision
   double kappa_limit;   // condition estimate above which a system is re-solved in FP64
+  double refine_kappa;  // mixed: condition estimate above which the FP64 correction runs
+  int refine;           // mixed: 0 = factor read-out only, 1 = FP64 correction
+  double route_tol;     // mixed read-out: error indicator above which a system is re-solved in FP64
+  int upd;              // mixed trailing updates: 0 FP32, 1 split FP16, 2 split BF16
   uint32_t* fallback;   // list of systems for the FP64 pass
   int step;             // upper bounding slice = lower + step (1: volume, 2: held-out slice)
   double* resid;        // leave-one-slice-out: z_hat - z per system

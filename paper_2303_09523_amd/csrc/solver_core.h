@@ -508,13 +508,14 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
 // wave (one atomic per wave instead of one per system).
 struct Tally {
   float kmax = 0.0f;
-  unsigned bad = 0, fp64 = 0;
+  unsigned bad = 0, fp64 = 0, failed = 0;
 };
 
 __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) {
   if ((threadIdx.x & 63) == 0) {
     if (t.bad) atomicAdd(&a.ctr->bad_pivot, (unsigned long long)t.bad);
     if (t.fp64) atomicAdd(&a.ctr->fp64_fallback, (unsigned long long)t.fp64);
+    if (t.failed) atomicAdd(&a.ctr->failed, (unsigned long long)t.failed);
     atomic_max_float(&a.ctr->max_kappa_bits, t.kmax);
   }
 }
@@ -523,12 +524,14 @@ __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) 
 // FP64 pass; updates flags and the wave's tallies.
 template <typename T>
 __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsigned sys, int cnt,
-                                              T est, T var, T mn, T mx, bool bad, Tally& tally) {
+                                              T est, T var, T mn, T mx, bool bad, Tally& tally,
+                                              bool route = false) {
   const int lane = threadIdx.x & 63;
   const Geometry& geo = a.geo;
   const int ntgt = geo.f - 1;
   const T kappa = mx / mn;
-  const bool fallback = mode == 0 && a.fallback && (bad || (double)kappa > a.kappa_limit);
+  const bool fallback =
+      mode == 0 && a.fallback && (bad || route || (double)kappa > a.kappa_limit);
   const unsigned plane = (unsigned)geo.plane;
   const unsigned gap = sys / plane;
   const unsigned pix = sys - gap * plane;
@@ -545,12 +548,14 @@ __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsi
   if (lane == 0 && a.flags) {
     uint8_t fl = (cnt & kFloorBit) ? kFlagFloor : 0;
     if (mode == 1) fl |= kFlagFp64;
+    if (mode == 1 && bad) fl |= kFlagFailed;
     if (bad && mode == 0) fl |= kFlagBadPivot;
     if (mode == 0) a.flags[sys] = fl;
     else a.flags[sys] |= fl;
   }
   if (bad && mode == 0) tally.bad += 1;
   if (mode == 1) tally.fp64 += 1;
+  if (mode == 1 && bad) tally.failed += 1;
   const float kf = (float)kappa;
   if (kf > tally.kmax && isfinite(kf)) tally.kmax = kf;
 }

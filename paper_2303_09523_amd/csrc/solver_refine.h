@@ -385,12 +385,16 @@ __device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, cons
   out1 = lane + 64 < n ? (a1[0] + a1[1]) + (a1[2] + a1[3]) : 0.0;
 }
 
-template <int NB, int UPD, typename MS>
-__device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& ws, const Smem<float>& sm,
+// Returns whether the FP64 correction ran: it does when CORR is set and the
+// pivot-ratio condition estimate exceeds refine_kappa; otherwise the estimate
+// is the factorisation's Schur read-out in the normalised units.
+template <int NB, int UPD, bool CORR, typename MS>
+__device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& ws, const Smem<float>& sm,
                                              MixedScratch& mx, const MS& ms, int ncand,
-                                             int ntgt, double sill, double* est_out,
-                                             float* var_out, float& mn, float& mxp, bool& bad,
-                                             double* w_out = nullptr, double* nu_scale = nullptr) {
+                                             int ntgt, double sill, double refine_kappa,
+                                             double* est_out, float* var_out, float& mn,
+                                             float& mxp, bool& bad, double* w_out = nullptr,
+                                             double* nu_scale = nullptr) {
   const int lane = threadIdx.x & 63;
   const int p0 = lane, p1 = lane + 64;
   // ---- 1. normalise the data ----
@@ -426,6 +430,20 @@ __device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& 
     *var_out = (float)(sill * (double)(1.0f - gtt + (1.0f - g1t) * m));
   }
   __builtin_amdgcn_wave_barrier();
+  if (!CORR || !((double)mxp > refine_kappa * (double)mn)) {
+    if (lane < ntgt) {
+      const int t = lane + 1;
+      const float g11 = ws.buf[ne * 17 + ne];
+      const float g1z = ws.buf[(ne + 1) * 17 + ne];
+      const float g1t = ws.buf[(ne + 1 + t) * 17 + ne];
+      const float gzt = ws.buf[(ne + 1 + t) * 17 + ne + 1];
+      const float m = (1.0f - g1t) / g11;
+      *est_out = (double)zref + ldexp((double)(gzt + m * g1z), ex);
+    }
+    if (nu_scale) *nu_scale = ldexp(1.0, ex);
+    __builtin_amdgcn_wave_barrier();
+    return false;
+  }
   // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' ----
   f32x4 Z[NB];
   back_substitute<NB, UPD>(nb, Ls, Xs, ws.buf, Z);
@@ -493,6 +511,7 @@ __device__ __forceinline__ void mixed_system(int n, int nb, WaveScratch<float>& 
   }
   if (nu_scale) *nu_scale = sd;
   __builtin_amdgcn_wave_barrier();
+  return true;
 }
 
 }  // namespace

@@ -27,13 +27,13 @@ def canonical_bits(kept):
 
 
 def run_gpu(slices, edge, f, r, vario, precision="fp32", algo="batched", min_points=4,
-            flags=False):
+            flags=False, **plan_kw):
     import torch
     import paper_2303_09523_amd as P
     n, ny, nx = slices.shape
     st = torch.from_numpy(np.ascontiguousarray(slices)).cuda()
     et = torch.from_numpy(np.ascontiguousarray(edge)).cuda() if edge is not None else None
-    plan = P.Plan(nx, ny, n, f, r, min_points, precision, algo)
+    plan = P.Plan(nx, ny, n, f, r, min_points, precision, algo, **plan_kw)
     vol, var, fl = plan.execute(st, vario, et, want_flags=flags)
     stats = plan.stats()
     out = (vol.cpu().numpy(), var.cpu().numpy(), None if fl is None else fl.cpu().numpy(), stats)
