@@ -2,21 +2,27 @@
 
 One step = one okr_execute over the whole synthetic volume: placement, table
 build, neighbour selection, size bucketing and the batched solve (one
-persistent launch per 16-wide size class, largest first) with, in the default
-mixed_fp16 precision, split-FP16 MFMA factorisation, back-substitution and the
-FP64 residual correction of every estimate, plus the FP64 re-solve of systems
-with a non-positive pivot. Inputs are resident in HBM before timing starts.
+persistent launch per 16-wide size class, largest first) plus the FP64 re-solve
+launch. The default is the mixed_fp16 read-out: split-FP16 MFMA trailing
+updates with FP32 accumulation, FP32 diagonal tiles, the Schur read-out, and an
+FP64 re-solve of systems with a non-positive pivot. Inputs are resident in HBM
+before timing starts; the launch shape comes from the library's autotuner and
+the timed steps replay the library's HIP graph of okr_execute.
 
 Prints ONE JSON line. Extra keys:
-  roofline       dominant kernel (batched solve): algorithmic FLOP per launch
-                 / mean launch time from HIP events recorded by the library
-  cpu_baseline   the FP64 oracle on a bounded random sample of the same
-                 systems, on this host's cores
-  plain_fp32     the per-voxel comparison kernel on a slab of the volume
-  batched_fp32   the batched path with FP32 factorisation (no correction)
-  accuracy       GPU result vs the oracle on that same sample
-  loso           leave-one-slice-out loss + adjoint gradient timing on the
-                 16 x 128^2 field workload
+  roofline          dominant kernel (the solve launches of one step):
+                    algorithmic FLOP / mean time from the library's HIP events
+                    over the same number of direct (non-graph) steps; traffic
+                    from the committed counter summary while the kernel sources
+                    are unchanged
+  cpu_baseline      the FP64 oracle on a bounded random sample of the same
+                    systems, on this host's cores
+  accuracy          the headline result vs the oracle on that sample
+  batched_variants  the other operating points (FP64-corrected mixed, FP64,
+                    FP32), each with its accuracy on the same sample
+  plain_fp32        the per-voxel comparison kernel on a slab of the volume
+  loso              leave-one-slice-out loss + adjoint gradient timing on the
+                    16 x 128^2 field workload
 """
 from __future__ import annotations
 
@@ -86,6 +92,44 @@ def cpu_baseline(w, s, e, target_s: float, seed: int = 12345):
                       f"{wall:.1f} s wall"}, (idx, est, var)
 
 
+TRAFFIC_SOURCES = ["okrig_internal.h", "solver_core.h", "solver_refine.h", "kernels_solve.hip",
+                   "kernels_mixed.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_09523_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(args):
+    """HBM bytes of one step's solve launches from the committed counter
+    summary (profiles/traffic_<workload>_<precision>_r<refine_max>.txt), or
+    None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles",
+                        f"traffic_{args.workload}_{args.precision}_r{args.refine_max}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["solve_hbm_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
+DTYPES = {"fp32": "f32", "fp64": "f64", "mixed_fp16": "f16x3+f32", "mixed_bf16": "bf16x3+f32"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,14 +137,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large_160x512")
     ap.add_argument("--precision", default="mixed_fp16")
-    ap.add_argument("--refine-max", type=int, default=1,
-                    help="mixed precisions: 0 = factorisation read-out only, 1 = FP64 correction")
+    ap.add_argument("--refine-max", type=int, default=0,
+                    help="mixed precisions: 0 = factorisation read-out, 1 = FP64 correction")
     ap.add_argument("--refine-tol", type=float, default=0.0,
                     help="refinement / routing threshold (okr_problem.refine_tol)")
+    ap.add_argument("--no-graph", action="store_true", help="direct launches instead of graph replay")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and LOSO extras")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other precisions and the leave-one-slice-out timing")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -129,43 +176,10 @@ def main():
     dev = torch.device("cuda:0")
     st = torch.from_numpy(s).to(dev)
     et = torch.from_numpy(e).to(dev) if e is not None else None
-    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
-                  refine_max=args.refine_max, refine_tol=args.refine_tol)
-    vol = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
-    var = torch.empty_like(vol)
-    for _ in range(args.warmup):
-        plan.execute(st, w.vario, et, volume=vol, variance=var)
-    torch.cuda.synchronize()
-    plan.stats()                     # clears counters
-    plan.set_profiling(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_host = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        plan.execute(st, w.vario, et, volume=vol, variance=var)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_host = time.perf_counter() - t_host
-    ms = ev0.elapsed_time(ev1) / args.steps
-    stats = plan.stats()
-    plan.set_profiling(False)
     kriged = w.kriged_voxels
-    value = kriged / (ms * 1e-3)
-
-    hist = np.array(stats["bucket"], dtype=np.float64)
-    nn = np.arange(len(hist), dtype=np.float64)
-    flops = float((hist * system_flops(nn, w.upsample)).sum())
-    solve_ms = stats["phase_ms"]["solve"] / max(1, stats["phase_calls"]["solve"])
-    achieved = flops / (solve_ms * 1e-3) / 1e12
-    # the factorisation's diagonal tiles, off-diagonal solves and back-substitution
-    # run on FP32 MFMA in every mode but fp64, and dominate its MFMA cycles
-    peak = PEAKS["fp64_tflops"] if args.precision == "fp64" else PEAKS["fp32_tflops"]
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 5), "traffic": None,
-            "kernel": "batched solve (all size-class launches of one step)",
-            "flop_per_launch": flops, "mean_launch_ms": round(solve_ms, 4)}
+    vol = torch.empty((w.upsample * (w.nslices - 1) + 1, w.m, w.m), dtype=torch.float32,
+                      device=dev)
+    var = torch.empty_like(vol)
 
     def accuracy(vol_t, var_t):
         if sample is None:
@@ -183,12 +197,75 @@ def main():
         zmax = float(np.abs(s).max())
         ee = np.abs(ge - est_o) / np.maximum(np.abs(est_o), 0.01 * zmax)
         evv = np.abs(gv - var_o) / w.vario.sill
-        return {"voxels": int(ee.size), "max_rel_err_est": float(ee.max()),
+        return {"voxels": int(ee.size),
+                "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max()),
+                "max_rel_err_est": float(ee.max()),
                 "p9999_rel_err_est": float(np.percentile(ee, 99.99)),
-                "max_rel_err_var": float(evv.max()),
-                "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max())}
+                "max_rel_err_var": float(evv.max())}
 
+    def timed(plan, steps, warmup):
+        for _ in range(warmup):
+            plan.execute(st, w.vario, et, volume=vol, variance=var)
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(steps):
+            plan.execute(st, w.vario, et, volume=vol, variance=var)
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) / steps
+
+    # ---- the headline path: timed graph replays of whole executes ----
+    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
+                  refine_max=args.refine_max, refine_tol=args.refine_tol)
+    tuning = None
+    if not args.no_tune:
+        tuning = plan.autotune(st, w.vario, et, volume=vol, variance=var)
+        print(f"# tuning {tuning}", file=sys.stderr, flush=True)
+    if not args.no_graph:
+        plan.set_graph(True)
+    for _ in range(args.warmup):
+        plan.execute(st, w.vario, et, volume=vol, variance=var)
+    torch.cuda.synchronize()
+    plan.stats()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        plan.execute(st, w.vario, et, volume=vol, variance=var)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = ev0.elapsed_time(ev1) / args.steps
+    stats = plan.stats()
+    value = kriged / (ms * 1e-3)
     acc = accuracy(vol, var)
+
+    # ---- the dominant kernel: the same steps with per-phase HIP events ----
+    plan.set_graph(False)
+    plan.set_profiling(True)
+    for _ in range(args.steps):
+        plan.execute(st, w.vario, et, volume=vol, variance=var)
+    pstats = plan.stats()
+    plan.set_profiling(False)
+    plan.close()
+    hist = np.array(pstats["bucket"], dtype=np.float64)
+    nn = np.arange(len(hist), dtype=np.float64)
+    flops = float((hist * system_flops(nn, w.upsample)).sum())
+    solve_ms = pstats["phase_ms"]["solve"] / max(1, pstats["phase_calls"]["solve"])
+    achieved = flops / (solve_ms * 1e-3) / 1e12
+    # the factorisation's diagonal tiles and off-diagonal solves run on FP32
+    # MFMA in every mode but fp64 and set its critical path
+    peak = PEAKS["fp64_tflops"] if args.precision == "fp64" else PEAKS["fp32_tflops"]
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": traffic_from_profiles(args),
+            "kernel": "batched solve (all size-class launches of one step)",
+            "flop_per_launch": flops, "mean_launch_ms": round(solve_ms, 4),
+            "timing": "library HIP events around the solve launches, same steps without graph"}
+
     calib = None
     if args.calib_copy > 0:
         src = torch.empty(args.calib_copy // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -199,24 +276,27 @@ def main():
         calib = {"copy_bytes": int(src.numel() * 4)}
         del src, dst
 
-    extra_fp32 = None
+    # ---- the other operating points of the batched path ----
+    others = {}
     loso = None
     if not args.no_extra:
-        if args.precision != "fp32":
-            p32 = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, "fp32", "batched")
-            p32.execute(st, w.vario, et, volume=vol, variance=var)
-            torch.cuda.synchronize()
-            b0 = torch.cuda.Event(enable_timing=True)
-            b1 = torch.cuda.Event(enable_timing=True)
-            b0.record()
-            for _ in range(2):
-                p32.execute(st, w.vario, et, volume=vol, variance=var)
-            b1.record()
-            torch.cuda.synchronize()
-            ms32 = b0.elapsed_time(b1) / 2
-            extra_fp32 = {"value": kriged / (ms32 * 1e-3), "unit": "voxels/s",
-                          "ms_per_step": round(ms32, 3), "accuracy": accuracy(vol, var)}
-            p32.close()
+        variants = [("mixed_fp16+fp64_correction", "mixed_fp16", 1), ("fp64", "fp64", 0),
+                    ("fp32", "fp32", 0), ("mixed_fp16_readout", "mixed_fp16", 0)]
+        for name, prec, rmax in variants:
+            if prec == args.precision and rmax == args.refine_max:
+                continue
+            pv = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, prec, "batched",
+                        refine_max=rmax)
+            pv.set_graph(True)
+            mv = timed(pv, 2, 1)
+            sv = pv.stats()
+            pv.close()
+            others[name] = {"value": kriged / (mv * 1e-3), "unit": "voxels/s",
+                            "ms_per_step": round(mv, 3), "dtype": DTYPES[prec] +
+                            ("+f64corr" if rmax else ""),
+                            "n_fp64_resolved": sv["n_fp64_fallback"],
+                            "accuracy": accuracy(vol, var)}
+            print(f"# {name}: {mv:.1f} ms", file=sys.stderr, flush=True)
         wl = W.workload("loso_16x128")
         sl_, _ = W.make_inputs(wl)
         slt = torch.from_numpy(sl_).to(dev)
@@ -265,31 +345,31 @@ def main():
                  "slab": f"first {sub} known slices ({pvox} kriged voxels)",
                  "batched_over_plain": round(value / (pvox / (pms * 1e-3)), 2)}
         pp.close()
-    plan.close()
 
     out = {
         "metric": "kriged voxels/sec, batched mixed vs plain FP32 at <=1e-5 rel err; % roofline",
         "value": value, "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64",
-                                                      "mixed_fp16": "f16x3+f32+f64corr",
-                                                      "mixed_bf16": "bf16x3+f32+f64corr"}.get(
-            args.precision, args.precision),
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPES.get(args.precision, args.precision) + ("+f64corr" if args.refine_max and
+                                                               args.precision.startswith("mixed")
+                                                               else ""),
         "data": "synthetic",
         "config": {"workload": w.name, "known_slices": w.nslices, "slice": f"{w.m}x{w.m}",
                    "upsample": w.upsample, "window": f"{2 * w.radius + 1}x{2 * w.radius + 1}x2",
                    "edge_mask": w.masked, "variogram": [w.vario.model, w.vario.nugget,
                                                          w.vario.sill, w.vario.range],
                    "kriged_voxels": kriged, "systems": w.systems,
-                   "precision": args.precision},
+                   "precision": args.precision, "refine_max": args.refine_max,
+                   "graph": not args.no_graph, "tuning": tuning},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "plain_fp32": plain,
-        "batched_fp32": extra_fp32,
         "accuracy": acc,
+        "plain_fp32": plain,
+        "batched_variants": others,
         "loso": loso,
         "calibration": calib,
-        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in stats["phase_ms"].items()},
+        "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in pstats["phase_ms"].items()},
         "solver_stats": {k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
                                                "n_nonpositive_pivot", "n_not_converged",
                                                "max_kappa_est")},
