@@ -184,6 +184,27 @@ okr_status okr_loso_forward(okr_plan* plan, const okr_variogram* vario, const fl
  * d_grad: device double[3]. OKR_E_INVALID_ARG if no forward preceded it. */
 okr_status okr_loso_backward(okr_plan* plan, double* d_grad);
 
+/* Ordinary kriging of explicitly given point sets (Appendix A with the single
+ * constant predictor), in FP64 whatever the plan's precision: the test seam
+ * for the closed forms and invariants of the method. System i has
+ * n_i = d_count[i] points (1..98) starting at d_offset[i] (CSR, int64):
+ *   d_xyz         float32 [total][3] point coordinates (x, y, z)
+ *   d_val         float32 [total] point values
+ *   d_target_xyz  float32 [nsys][3] one target per system
+ *   d_est         float32 [nsys] estimate (required)
+ *   d_var         float32 [nsys] kriging variance sill - w'c0 - mu (nullable)
+ *   d_weights     float32 [total] weights w, CSR like d_val (nullable)
+ * Covariance: Cov(0) = sill, Cov(h > 0) = (sill - nugget) rho(h) on Euclidean
+ * distances. All device buffers are caller-owned; stream-ordered. A count
+ * outside 1..98 gives NaN outputs for that system and OKR_E_SHAPE at the next
+ * okr_stats_get; a non-positive pivot (e.g. coincident points with nugget 0)
+ * gives NaN outputs and is counted in n_nonpositive_pivot; non-finite inputs
+ * give OKR_E_NONFINITE at the next okr_stats_get. */
+okr_status okr_krige_points(okr_plan* plan, const okr_variogram* vario, int64_t nsys,
+                            const int32_t* d_count, const int64_t* d_offset, const float* d_xyz,
+                            const float* d_val, const float* d_target_xyz, float* d_est,
+                            float* d_var, float* d_weights);
+
 /* Counters of the last execute / loso call; synchronises the plan's stream and
  * returns any latched device-side error (e.g. OKR_E_NONFINITE). */
 okr_status okr_stats_get(okr_plan* plan, okr_stats* out);

@@ -131,6 +131,29 @@ class Plan:
         _lib.check(load().okr_plan_get_tuning(self._h, C.byref(g), C.byref(u), ms), self._h)
         return {"grid_per_cu": g.value, "update_arith": u.value, "candidate_ms": list(ms)}
 
+    def krige_points(self, count, offset, xyz, val, target_xyz, vario, want_weights=False):
+        """FP64 ordinary kriging of explicit point sets (okr_krige_points).
+
+        count int32 [S], offset int64 [S] (CSR), xyz float32 [T][3], val float32
+        [T], target_xyz float32 [S][3]; returns (est [S], var [S], weights [T] or
+        None), all CUDA float32."""
+        torch = _torch()
+        S = int(count.numel())
+        for t, dt, nm in ((count, torch.int32, "count"), (offset, torch.int64, "offset"),
+                          (xyz, torch.float32, "xyz"), (val, torch.float32, "val"),
+                          (target_xyz, torch.float32, "target_xyz")):
+            if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"{nm} must be a contiguous CUDA {dt} tensor")
+        est = torch.empty(S, dtype=torch.float32, device=count.device)
+        var = torch.empty(S, dtype=torch.float32, device=count.device)
+        w = torch.empty(val.numel(), dtype=torch.float32, device=count.device) if want_weights \
+            else None
+        v = _as_vario(vario)
+        _lib.check(load().okr_krige_points(self._h, C.byref(v), S, _ptr(count), _ptr(offset),
+                                           _ptr(xyz), _ptr(val), _ptr(target_xyz), _ptr(est),
+                                           _ptr(var), _ptr(w)), self._h)
+        return est, var, w
+
     def select(self, edge=None):
         """Kept-candidate bitmasks [(n-1)*ny*nx][2] (int64 view of uint64) and counts."""
         torch = _torch()

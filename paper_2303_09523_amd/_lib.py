@@ -23,7 +23,8 @@ ALGOS = {"batched": 0, "plain": 1}
 EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
             "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling",
-            "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning"]
+            "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning",
+            "okr_krige_points"]
 
 
 class Variogram(C.Structure):
@@ -79,6 +80,8 @@ def load():
         "okr_abi_sizes": (C.c_int32, [P(C.c_int64)]),
         "okr_plan_set_profiling": (C.c_int32, [VP, C.c_int32]),
         "okr_plan_set_graph": (C.c_int32, [VP, C.c_int32]),
+        "okr_krige_points": (C.c_int32, [VP, P(Variogram), C.c_int64, VP, VP, VP, VP, VP, VP,
+                                         VP, VP]),
         "okr_plan_autotune": (C.c_int32, [VP, P(Variogram), VP, VP, VP, VP]),
         "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double)]),
     }

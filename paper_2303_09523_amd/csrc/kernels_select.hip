@@ -10,41 +10,10 @@
 //             an LDS tile of both slices' edge masks.
 //  * bucket:  counting sort of the systems by neighbour count, largest first.
 #include "okrig_internal.h"
+#include "variogram.h"
 
 namespace okr {
 namespace {
-
-__device__ double rho_d(int model, double h, double a) {
-  if (model == 0) {
-    double q = h / a;
-    return q < 1.0 ? 1.0 - 1.5 * q + 0.5 * q * q * q : 0.0;
-  }
-  if (model == 1) return exp(-3.0 * h / a);
-  double q = h / a;
-  return exp(-3.0 * q * q);
-}
-
-__device__ double drho_da_d(int model, double h, double a) {
-  if (model == 0) {
-    double q = h / a;
-    return q < 1.0 ? 1.5 * h / (a * a) - 1.5 * h * h * h / (a * a * a * a) : 0.0;
-  }
-  if (model == 1) return exp(-3.0 * h / a) * 3.0 * h / (a * a);
-  double q = h / a;
-  return exp(-3.0 * q * q) * 6.0 * h * h / (a * a * a);
-}
-
-__device__ void cov_and_grad(const Vario v, double h, double* c, double* dn, double* ds, double* da) {
-  if (h == 0.0) {
-    *c = v.sill; *dn = 0.0; *ds = 1.0; *da = 0.0;
-    return;
-  }
-  double rho = rho_d(v.model, h, v.range);
-  *c = (v.sill - v.nugget) * rho;
-  *dn = -rho;
-  *ds = rho;
-  *da = (v.sill - v.nugget) * drho_da_d(v.model, h, v.range);
-}
 
 __global__ void tables_kernel(Vario v, int f, int r, TableSet t) {
   for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) {
@@ -98,6 +67,7 @@ __global__ void reset_kernel(DevCounters* c) {
     c->max_kappa_bits = 0;
     c->zmax_bits = 0;
     c->nonfinite = 0;
+    c->bad_input = 0;
     c->offsets[kHist] = 0;
     c->n_fallback_list = 0;
   }

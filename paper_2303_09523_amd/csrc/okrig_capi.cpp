@@ -617,6 +617,27 @@ okr_status okr_plan_get_tuning(const okr_plan* p, int32_t* grid_per_cu, int32_t*
   return OKR_OK;
 }
 
+okr_status okr_krige_points(okr_plan* p, const okr_variogram* vario, int64_t nsys,
+                            const int32_t* d_count, const int64_t* d_offset, const float* d_xyz,
+                            const float* d_val, const float* d_target_xyz, float* d_est,
+                            float* d_var, float* d_weights) {
+  if (!p) return OKR_E_INVALID_ARG;
+  std::string msg;
+  okr_status st = validate_vario(vario, &msg);
+  if (st != OKR_OK) return fail(p, st, msg);
+  if (nsys < 0) return fail(p, OKR_E_INVALID_ARG, "nsys must be >= 0");
+  if (nsys > 0 && (!d_count || !d_offset || !d_xyz || !d_val || !d_target_xyz || !d_est))
+    return fail(p, OKR_E_INVALID_ARG, "count, offset, xyz, val, target_xyz and est are required");
+  p->loso_ready = false;
+  OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_points(vario_of(vario), (long long)nsys, d_count, d_offset, d_xyz, d_val,
+                                d_target_xyz, d_est, d_var, d_weights, p->ctr, p->num_cu * 4,
+                                p->stream));
+  p->last_nsys = nsys;
+  p->last_kriged = nsys;
+  return OKR_OK;
+}
+
 okr_status okr_plan_set_graph(okr_plan* p, int32_t enable) {
   if (!p) return OKR_E_INVALID_ARG;
   p->use_graph = enable != 0;
@@ -736,6 +757,7 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
   }
   out->n_not_converged = (int64_t)c.failed;
   if (c.nonfinite) return fail(p, OKR_E_NONFINITE, "a known voxel is not finite");
+  if (c.bad_input) return fail(p, OKR_E_SHAPE, "a point system has a count outside 1..98");
   if (p->prob.strict && c.failed)
     return fail(p, OKR_E_NOT_CONVERGED, "a system met a non-positive pivot in FP64 as well");
   return OKR_OK;

@@ -59,6 +59,7 @@ struct DevCounters {
   unsigned int max_kappa_bits;      // float bits of the largest estimate
   unsigned int zmax_bits;           // float bits of the largest |known voxel|
   unsigned int nonfinite;           // nonzero if a known voxel is not finite
+  unsigned int bad_input;           // nonzero if a point system had an invalid count
   unsigned long long offsets[kHist + 1];  // bucket starts (largest n first)
   unsigned long long cursor[kHist];
   unsigned long long next2;         // second-pass cursor
@@ -108,6 +109,12 @@ hipError_t launch_solve_fallback(const SolveArgs& a, int grid, hipStream_t s);
 int solve_blocks_needed(const Geometry& g);
 
 hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
+
+// ---- launcher (kernels_points.hip) ----
+hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
+                         const int64_t* offset, const float* xyz, const float* val,
+                         const float* txyz, float* est, float* var, float* weights,
+                         DevCounters* c, int grid, hipStream_t s);
 
 // ---- launchers (kernels_adjoint.hip) ----
 hipError_t launch_loso_forward(const SolveArgs& a, int grid, hipStream_t s);
