@@ -77,8 +77,14 @@ typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 
 /* BATCHED: selection, size bucketing and one persistent factorisation launch,
  * one Cholesky per (column, gap) shared by its f-1 targets.
  * PLAIN_PER_VOXEL: one bordered LU (partial pivoting) per kriged voxel with
- * direct covariance evaluation; the comparison kernel. */
-typedef enum { OKR_ALGO_BATCHED = 0, OKR_ALGO_PLAIN_PER_VOXEL = 1 } okr_algo;
+ * direct covariance evaluation; the comparison kernel.
+ * PATTERN_CACHE: BATCHED, except that the systems keeping the whole window
+ * (the same matrix for all of them, by translation invariance) take weights
+ * and variances computed once per launch in FP64 and applied as FP64 dot
+ * products; the other systems are solved as in BATCHED at the plan's
+ * precision. */
+typedef enum { OKR_ALGO_BATCHED = 0, OKR_ALGO_PLAIN_PER_VOXEL = 1,
+               OKR_ALGO_PATTERN_CACHE = 2 } okr_algo;
 
 typedef struct {
   int32_t model;        /* okr_model */
@@ -126,11 +132,12 @@ typedef struct {
   int64_t n_fp64_fallback;    /* systems re-solved in FP64 */
   int64_t n_nonpositive_pivot;/* systems with a non-positive pivot in the first pass */
   double  max_kappa_est;      /* largest pivot-ratio condition estimate */
-  double  phase_ms[8];        /* with profiling on: summed device time per phase since the
+  double  phase_ms[10];       /* with profiling on: summed device time per phase since the
                                  last okr_stats_get: 0 placement, 1 tables, 2 selection,
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
-                                 6 plain per-voxel kernel, 7 leave-one-slice-out */
-  int64_t phase_calls[8];     /* launches timed per phase */
+                                 6 plain per-voxel kernel, 7 leave-one-slice-out,
+                                 8 full-window pattern weights + application, 9 unused */
+  int64_t phase_calls[10];    /* launches timed per phase */
   int64_t n_not_converged;    /* systems whose FP64 re-solve also met a non-positive pivot */
 } okr_stats;
 
@@ -142,6 +149,8 @@ typedef struct {
 #define OKR_PHASE_FALLBACK 5
 #define OKR_PHASE_PLAIN 6
 #define OKR_PHASE_LOSO 7
+#define OKR_PHASE_PATTERN 8
+#define OKR_NUM_PHASES 10
 
 /* Create a plan for one problem shape. `hip_stream` is a hipStream_t (NULL =
  * the default stream). Validates every field (OKR_E_INVALID_ARG / SHAPE /

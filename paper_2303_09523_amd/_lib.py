@@ -16,9 +16,9 @@ STATUS_NAMES = {0: "OKR_OK", 1: "OKR_E_INVALID_ARG", 2: "OKR_E_SHAPE", 3: "OKR_E
                 4: "OKR_E_DEVICE", 5: "OKR_E_OOM", 6: "OKR_E_UNSUPPORTED",
                 7: "OKR_E_NOT_CONVERGED"}
 MODELS = {"spherical": 0, "exponential": 1, "gaussian": 2}
-PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso"]
+PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso", "pattern"]
 PRECISIONS = {"fp32": 0, "mixed_fp16": 1, "mixed_bf16": 2, "fp64": 3}
-ALGOS = {"batched": 0, "plain": 1}
+ALGOS = {"batched": 0, "plain": 1, "pattern": 2}
 
 EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
@@ -43,8 +43,8 @@ class Stats(C.Structure):
     _fields_ = [("n_systems", C.c_int64), ("n_kriged", C.c_int64), ("bucket", C.c_int64 * 128),
                 ("n_floor_filled", C.c_int64), ("n_refined", C.c_int64),
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
-                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 8),
-                ("phase_calls", C.c_int64 * 8), ("n_not_converged", C.c_int64)]
+                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 10),
+                ("phase_calls", C.c_int64 * 10), ("n_not_converged", C.c_int64)]
 
 
 class OkrError(RuntimeError):

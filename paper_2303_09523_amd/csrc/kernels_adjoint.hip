@@ -46,6 +46,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
   if (nlo < 1) nlo = 1;
   if (nhi > kHist - 1) nhi = kHist - 1;
+  if (nhi > a.nmax) nhi = a.nmax;
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];

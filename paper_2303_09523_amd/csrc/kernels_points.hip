@@ -34,6 +34,76 @@ __device__ __forceinline__ double wave_sum(double x) {
   return lane_d(x, 0);
 }
 
+// C = L L^T in place in the lower triangle of A (row stride kPtLd), lanes over
+// rows. Returns true (uniformly) on a non-positive pivot.
+__device__ bool chol_lds(double* A, int n) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < n; ++k) {
+    const double d = A[k * kPtLd + k];
+    if (!(d > 0.0)) return true;
+    const double is = 1.0 / sqrt(d);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i > k && i < n) A[i * kPtLd + k] *= is;
+    }
+    if (lane == 0) A[k * kPtLd + k] = d * is;   // L[k][k] = sqrt(d)
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i > k && i < n) {
+        const double lik = A[i * kPtLd + k];
+        for (int j = k + 1; j <= i; ++j) A[i * kPtLd + j] -= lik * A[j * kPtLd + k];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  return false;
+}
+
+// Solves L L^T x = b for two right-hand sides held by rows (b[h] of lane l is
+// row l + 64 h); on return b holds x.
+__device__ void subst_lds(const double* A, int n, double (&b)[2], double (&c)[2]) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < n; ++k) {
+    const double lkk = A[k * kPtLd + k];
+    const int hk = k >> 6, lk = k & 63;
+    const double yb = (hk ? lane_d(b[1], lk) : lane_d(b[0], lk)) / lkk;
+    const double yc = (hk ? lane_d(c[1], lk) : lane_d(c[0], lk)) / lkk;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i == k) {
+        b[h] = yb;
+        c[h] = yc;
+      } else if (i > k && i < n) {
+        const double lik = A[i * kPtLd + k];
+        b[h] -= lik * yb;
+        c[h] -= lik * yc;
+      }
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double lkk = A[k * kPtLd + k];
+    const int hk = k >> 6, lk = k & 63;
+    const double xb = (hk ? lane_d(b[1], lk) : lane_d(b[0], lk)) / lkk;
+    const double xc = (hk ? lane_d(c[1], lk) : lane_d(c[0], lk)) / lkk;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i == k) {
+        b[h] = xb;
+        c[h] = xc;
+      } else if (i < k) {
+        const double lki = A[k * kPtLd + i];
+        b[h] -= lki * xb;
+        c[h] -= lki * xc;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
                                                     const int32_t* __restrict__ count,
                                                     const int64_t* __restrict__ offset,
@@ -89,32 +159,7 @@ __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // right-looking Cholesky, C = L L^T in the lower triangle
-    bool bad = false;
-    for (int k = 0; k < n; ++k) {
-      const double d = A[k * kPtLd + k];
-      if (!(d > 0.0)) {
-        bad = true;
-        break;
-      }
-      const double is = 1.0 / sqrt(d);
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        if (i > k && i < n) A[i * kPtLd + k] *= is;
-      }
-      if (lane == 0) A[k * kPtLd + k] = d * is;   // L[k][k] = sqrt(d)
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        if (i > k && i < n) {
-          const double lik = A[i * kPtLd + k];
-          for (int j = k + 1; j <= i; ++j) A[i * kPtLd + j] -= lik * A[j * kPtLd + k];
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-    }
+    const bool bad = chol_lds(A, n);
     if (bad) {
       if (lane == 0) {
         atomicAdd(&ctr->bad_pivot, 1ull);
@@ -128,49 +173,14 @@ __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
       }
       continue;
     }
-    // two right-hand sides: b = 1 and b = c0; forward then back substitution
+    // two right-hand sides: b = 1 and b = c0
     double b1[2], bc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       b1[h] = lane + 64 * h < n ? 1.0 : 0.0;
       bc[h] = c0[h];
     }
-    for (int k = 0; k < n; ++k) {
-      const double lkk = A[k * kPtLd + k];
-      const int hk = k >> 6, lk = k & 63;
-      const double y1 = (hk ? lane_d(b1[1], lk) : lane_d(b1[0], lk)) / lkk;
-      const double yc = (hk ? lane_d(bc[1], lk) : lane_d(bc[0], lk)) / lkk;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        if (i == k) {
-          b1[h] = y1;
-          bc[h] = yc;
-        } else if (i > k && i < n) {
-          const double lik = A[i * kPtLd + k];
-          b1[h] -= lik * y1;
-          bc[h] -= lik * yc;
-        }
-      }
-    }
-    for (int k = n - 1; k >= 0; --k) {
-      const double lkk = A[k * kPtLd + k];
-      const int hk = k >> 6, lk = k & 63;
-      const double x1 = (hk ? lane_d(b1[1], lk) : lane_d(b1[0], lk)) / lkk;
-      const double xc = (hk ? lane_d(bc[1], lk) : lane_d(bc[0], lk)) / lkk;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        if (i == k) {
-          b1[h] = x1;
-          bc[h] = xc;
-        } else if (i < k) {
-          const double lki = A[k * kPtLd + i];
-          b1[h] -= lki * x1;
-          bc[h] -= lki * xc;
-        }
-      }
-    }
+    subst_lds(A, n, b1, bc);
     const double s1 = wave_sum(b1[0] + b1[1]);
     const double sc = wave_sum(bc[0] + bc[1]);
     const double mu = (sc - 1.0) / s1;
@@ -189,6 +199,124 @@ __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
   }
 }
 
+// ---- exact cache of the full-window pattern ----
+// Systems that keep every candidate of the window share their matrix: the
+// covariances depend only on the offsets (translation invariance). Their
+// weights w_t and variances are computed once per launch in FP64 (one wave),
+// and each such system is then a gather of its values and f-1 dot products.
+
+// Candidate c of the window -> (dx, dy, s) with the canonical index
+// c = s W^2 + (dy + r) W + (dx + r).
+__device__ __forceinline__ void cand_xyz(int c, const Geometry& g, int* dx, int* dy, int* s) {
+  *s = c >= g.W2;
+  const int o = c - *s * g.W2;
+  *dy = o / g.W - g.r;
+  *dx = o - (o / g.W) * g.W - g.r;
+}
+
+__global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g, double* W,
+                                                             double* wvar, DevCounters* ctr) {
+  __shared__ double A[kPtMax * kPtLd];
+  const int lane = threadIdx.x;
+  const int n = g.ncand;
+  for (int i = lane; i < n; i += 64) {
+    int dxi, dyi, si;
+    cand_xyz(i, g, &dxi, &dyi, &si);
+    for (int j = 0; j <= i; ++j) {
+      int dxj, dyj, sj;
+      cand_xyz(j, g, &dxj, &dyj, &sj);
+      const double ddx = dxi - dxj, ddy = dyi - dyj, ddz = (double)(si - sj) * g.f;
+      A[i * kPtLd + j] = i == j ? v.sill : cov_d(v, sqrt(ddx * ddx + ddy * ddy + ddz * ddz));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (chol_lds(A, n)) {
+    if (lane == 0) atomicAdd(&ctr->bad_pivot, 1ull);
+    for (int t = 0; t < g.f - 1; ++t) {
+      for (int i = lane; i < n; i += 64) W[t * kMaxCand + i] = __builtin_nan("");
+      if (lane == 0) wvar[t] = __builtin_nan("");
+    }
+    return;
+  }
+  for (int t = 1; t < g.f; ++t) {
+    double b1[2], bc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      b1[h] = i < n ? 1.0 : 0.0;
+      bc[h] = 0.0;
+      if (i < n) {
+        int dx, dy, sc;
+        cand_xyz(i, g, &dx, &dy, &sc);
+        const double dz = (double)sc * g.f - t;
+        bc[h] = cov_d(v, sqrt((double)(dx * dx + dy * dy) + dz * dz));
+      }
+    }
+    const double c0[2] = {bc[0], bc[1]};
+    subst_lds(A, n, b1, bc);
+    const double s1 = wave_sum(b1[0] + b1[1]);
+    const double sc = wave_sum(bc[0] + bc[1]);
+    const double mu = (sc - 1.0) / s1;
+    const double w0 = bc[0] - mu * b1[0], w1 = bc[1] - mu * b1[1];
+    const double wc = wave_sum(w0 * c0[0] + w1 * c0[1]);
+    if (lane < n) W[(t - 1) * kMaxCand + lane] = w0;
+    if (lane + 64 < n) W[(t - 1) * kMaxCand + lane + 64] = w1;
+    if (lane == 0) wvar[t - 1] = v.sill - wc - mu;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// One thread per full-window system of the size-sorted list (the bucket of
+// n = ncand): gathers its values and applies the cached weights in FP64.
+__global__ __launch_bounds__(256) void pattern_apply_kernel(const float* __restrict__ slices,
+                                                            const uint32_t* __restrict__ perm,
+                                                            const DevCounters* __restrict__ ctr,
+                                                            Geometry g, const double* __restrict__ W,
+                                                            const double* __restrict__ wvar,
+                                                            float* __restrict__ volume,
+                                                            float* __restrict__ variance,
+                                                            uint8_t* __restrict__ flags) {
+  __shared__ double ws[(kMaxUpsample - 1) * kMaxCand];
+  __shared__ double vs[kMaxUpsample];
+  __shared__ long long off[kMaxCand];
+  const int n = g.ncand, nt = g.f - 1;
+  for (int i = threadIdx.x; i < nt * kMaxCand; i += blockDim.x) ws[i] = W[i];
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) vs[i] = wvar[i];
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    int dx, dy, s;
+    cand_xyz(c, g, &dx, &dy, &s);
+    off[c] = (long long)s * g.plane + (long long)dy * g.nx + dx;
+  }
+  __syncthreads();
+  const unsigned long long start = ctr->offsets[n];
+  const unsigned long long cnt = ctr->hist[n];
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < cnt;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned sys = perm[start + i];
+    const unsigned gap = sys / (unsigned)g.plane;
+    const unsigned pix = sys - gap * (unsigned)g.plane;
+    const int y = (int)(pix / (unsigned)g.nx), x = (int)(pix - (unsigned)y * (unsigned)g.nx);
+    // a kept full window lies inside the image; checked, not assumed
+    if (x < g.r || y < g.r || x + g.r >= g.nx || y + g.r >= g.ny) continue;
+    const float* base = slices + (long long)gap * g.plane + pix;
+    double acc[kMaxUpsample - 1];
+#pragma unroll
+    for (int t = 0; t < kMaxUpsample - 1; ++t) acc[t] = 0.0;
+    for (int c = 0; c < n; ++c) {
+      const double z = base[off[c]];
+#pragma unroll
+      for (int t = 0; t < kMaxUpsample - 1; ++t)
+        if (t < nt) acc[t] += ws[t * kMaxCand + c] * z;
+    }
+    for (int t = 0; t < nt; ++t) {
+      const long long o = ((long long)gap * g.f + t + 1) * g.plane + pix;
+      volume[o] = (float)acc[t];
+      if (variance) variance[o] = (float)vs[t];
+    }
+    if (flags) flags[sys] = 0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
@@ -199,6 +327,21 @@ hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
   const long long g = nsys < grid ? nsys : grid;
   hipLaunchKernelGGL(points_kernel, dim3((unsigned)g), dim3(64), 0, s, v, nsys, count, offset,
                      xyz, val, txyz, est, var, weights, c);
+  return hipGetLastError();
+}
+
+}  // namespace okr
+
+namespace okr {
+
+hipError_t launch_pattern(const float* slices, const uint32_t* perm, DevCounters* c,
+                          const Geometry& g, const Vario& v, double* W, double* wvar,
+                          float* volume, float* variance, uint8_t* flags, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(64), 0, s, v, g, W, wvar, c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pattern_apply_kernel, dim3(grid), dim3(256), 0, s, slices, perm, c, g, W,
+                     wvar, volume, variance, flags);
   return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ struct okr_plan {
   uint8_t* count = nullptr;
   uint32_t* perm = nullptr;
   uint32_t* fallback = nullptr;
+  double* pattern_w = nullptr;  // full-window weights [f-1][kMaxCand] and variances [f-1]
   okr::DevCounters* ctr = nullptr;
   double* tabs = nullptr;       // FP64 tables and derivatives
   float* tabs_f = nullptr;      // FP32 copies
@@ -70,8 +71,8 @@ struct okr_plan {
   long long graph_launches = 0, graph_captures = 0;
   struct Mark { int phase; hipEvent_t a, b; };
   std::vector<Mark> marks;
-  double phase_ms[8] = {0};
-  long long phase_calls[8] = {0};
+  double phase_ms[OKR_NUM_PHASES] = {0};
+  long long phase_calls[OKR_NUM_PHASES] = {0};
   std::string err;
 };
 
@@ -144,7 +145,8 @@ okr_status validate_problem(const okr_problem* p, std::string* msg) {
     *msg = "unknown precision";
     return OKR_E_INVALID_ARG;
   }
-  if (p->algo != OKR_ALGO_BATCHED && p->algo != OKR_ALGO_PLAIN_PER_VOXEL) {
+  if (p->algo != OKR_ALGO_BATCHED && p->algo != OKR_ALGO_PLAIN_PER_VOXEL &&
+      p->algo != OKR_ALGO_PATTERN_CACHE) {
     *msg = "unknown algo";
     return OKR_E_INVALID_ARG;
   }
@@ -211,6 +213,7 @@ void free_plan(okr_plan* p) {
   hipFree(p->count);
   hipFree(p->perm);
   hipFree(p->fallback);
+  hipFree(p->pattern_w);
   hipFree(p->ctr);
   hipFree(p->tabs);
   hipFree(p->tabs_f);
@@ -256,6 +259,7 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.refine = 0;
   a.route_tol = 0.0;
   a.upd = 1;
+  a.nmax = okr::kHist - 1;
   a.fallback = nullptr;
   a.step = 1;
   a.resid = nullptr;
@@ -373,7 +377,12 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
     free_plan(p);
     return st;
   }
-  if (problem->algo == OKR_ALGO_BATCHED) {
+  if (problem->algo != OKR_ALGO_PLAIN_PER_VOXEL) {
+    if ((st = dev_alloc(p, &p->pattern_w, (okr::kMaxUpsample - 1) * okr::kMaxCand + okr::kMaxUpsample)) !=
+        OKR_OK) {
+      free_plan(p);
+      return st;
+    }
     if ((st = dev_alloc(p, &p->bits, 2 * nsys)) != OKR_OK ||
         (st = dev_alloc(p, &p->count, nsys)) != OKR_OK ||
         (st = dev_alloc(p, &p->perm, nsys)) != OKR_OK ||
@@ -437,6 +446,14 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   a.volume = d_volume;
   a.variance = d_variance;
   a.flags = d_flags;
+  if (p->prob.algo == OKR_ALGO_PATTERN_CACHE) {
+    // the full-window systems from the cached FP64 weights; the rest below
+    PhaseTimer t(p, OKR_PHASE_PATTERN);
+    OKR_HIP(p, okr::launch_pattern(d_slices, p->perm, p->ctr, g, vario_of(vario), p->pattern_w,
+                                   p->pattern_w + (okr::kMaxUpsample - 1) * okr::kMaxCand,
+                                   d_volume, d_variance, d_flags, p->num_cu * 8, strm));
+    a.nmax = g.ncand - 1;
+  }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
   // condition estimate x FP32 unit roundoff above refine_tol: FP32 systems go
   // to the FP64 re-solve, mixed systems take the FP64 correction; without the
@@ -553,7 +570,7 @@ okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const floa
   okr_status st = validate_vario(vario, &msg);
   if (st != OKR_OK) return fail(p, st, msg);
   if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
-  if (p->prob.algo != OKR_ALGO_BATCHED || p->geo.nslices < 2 || p->geo.f < 2) {
+  if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL || p->geo.nslices < 2 || p->geo.f < 2) {
     p->tuned = true;
     return OKR_OK;
   }
@@ -670,7 +687,7 @@ okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float
   okr_status st = validate_vario(vario, &msg);
   if (st != OKR_OK) return fail(p, st, msg);
   if (!d_slices || !d_loss) return fail(p, OKR_E_INVALID_ARG, "slices and loss are required");
-  if (p->prob.algo != OKR_ALGO_BATCHED)
+  if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL)
     return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out needs a batched plan");
   if (p->geo.f != 2)
     return fail(p, OKR_E_UNSUPPORTED,
@@ -749,7 +766,7 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
   std::memcpy(&k, &c.max_kappa_bits, sizeof(k));
   out->max_kappa_est = k;
   drain_marks(p);
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < OKR_NUM_PHASES; ++i) {
     out->phase_ms[i] = p->phase_ms[i];
     out->phase_calls[i] = p->phase_calls[i];
     p->phase_ms[i] = 0.0;

@@ -98,6 +98,7 @@ struct SolveArgs {
   int refine;           // mixed: 0 = factor read-out only, 1 = FP64 correction
   double route_tol;     // mixed read-out: error indicator above which a system is re-solved in FP64
   int upd;              // mixed trailing updates: 0 FP32, 1 split FP16, 2 split BF16
+  int nmax;             // largest neighbour count the size-class kernels take
   uint32_t* fallback;   // list of systems for the FP64 pass
   int step;             // upper bounding slice = lower + step (1: volume, 2: held-out slice)
   double* resid;        // leave-one-slice-out: z_hat - z per system
@@ -110,7 +111,10 @@ int solve_blocks_needed(const Geometry& g);
 
 hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
 
-// ---- launcher (kernels_points.hip) ----
+// ---- launchers (kernels_points.hip) ----
+hipError_t launch_pattern(const float* slices, const uint32_t* perm, DevCounters* c,
+                          const Geometry& g, const Vario& v, double* W, double* wvar,
+                          float* volume, float* variance, uint8_t* flags, int grid, hipStream_t s);
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
                          const int64_t* offset, const float* xyz, const float* val,
                          const float* txyz, float* est, float* var, float* weights,

@@ -313,3 +313,62 @@ def test_mixed_error_routing(oracle_cache):
     ee = rel_err_est(vr[kz], vol_o[kz], np.abs(s).max())
     print(f"routed max est err {ee.max():.3e}", flush=True)
     assert ee.max() <= TOL["mixed_fp16"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("precision", ["fp32", "mixed_fp16"])
+def test_pattern_cache_vs_oracle(case, precision, oracle_cache):
+    """PATTERN_CACHE: full-window systems from the cached FP64 weights, the rest
+    batched; the same bars as the batched path."""
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, e, vol_o, var_o, npts = _oracle(oracle_cache, case)
+    vol, var, fl, st = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision=precision,
+                               algo="pattern", min_points=min(4, 2 * (2 * r + 1) ** 2))
+    np.testing.assert_array_equal(vol[::f], s)
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    zmax = np.abs(s).max()
+    ee = rel_err_est(vol[kz], vol_o[kz], zmax)
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    nw = np.abs(vol[kz].astype(np.float64) - vol_o[kz]).max() / np.abs(vol_o[kz]).max()
+    print(f"case {name} pattern {precision}: est {ee.max():.3e} var {ev.max():.3e} "
+          f"normwise {nw:.3e} full-window systems {st['bucket'][2 * (2 * r + 1) ** 2]}",
+          flush=True)
+    assert ee.max() <= TOL[precision]
+    assert ev.max() <= max(TOL[precision], 1e-5)
+    if precision == "fp32":
+        assert nw <= NORMWISE_FP32
+    assert st["bucket"] == np.bincount(npts.ravel(), minlength=128).tolist()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]], ids=[CASES[0][0], CASES[2][0]])
+def test_pattern_cache_splits_exactly(case):
+    """Systems that do not keep the whole window are bit-identical to the
+    batched launch; full-window systems match the FP64 batched solve to float32
+    rounding."""
+    import torch
+    import paper_2303_09523_amd as P
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    s, _ = _inputs(name, n, ny, nx, f, r, masked, seed)
+    e = W.sobel_edges(s) if masked else None      # phantom edges only: full windows exist
+    vario = (model, nug, sill, rng_)
+    mp = min(4, 2 * (2 * r + 1) ** 2)
+    vb, wb, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", min_points=mp, refine_max=0)
+    vp, wp, fp, sp = run_gpu(s, e, f, r, vario, precision="mixed_fp16", min_points=mp,
+                             algo="pattern", refine_max=0, flags=True)
+    v64, w64, _, _ = run_gpu(s, e, f, r, vario, precision="fp64", min_points=mp)
+    plan = P.Plan(nx, ny, n, f, r, mp)
+    _, count = plan.select(torch.from_numpy(e).cuda() if e is not None else None)
+    plan.close()
+    full = ((count.cpu().numpy() & 0x7f) == 2 * (2 * r + 1) ** 2).reshape(n - 1, ny, nx)
+    print(f"full-window systems {full.sum()} of {full.size}", flush=True)
+    assert full.sum() > 0
+    zmax = np.abs(s).max()
+    for g in range(n - 1):
+        for t in range(1, f):
+            z = g * f + t
+            m = full[g]
+            np.testing.assert_array_equal(vp[z][~m], vb[z][~m])
+            np.testing.assert_array_equal(wp[z][~m], wb[z][~m])
+            assert rel_err_est(vp[z][m], v64[z][m].astype(np.float64), zmax).max() <= 1.2e-7
+            assert np.abs(wp[z][m] - w64[z][m]).max() <= 1.2e-7 * sill
