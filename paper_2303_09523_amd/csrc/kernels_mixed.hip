@@ -33,9 +33,10 @@ namespace {
 constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;   // 2^-24
 
 // Without the correction the kernel holds only the factorisation's live tiles
-// and is compiled for two waves per SIMD, like the FP32 kernel.
+// and is compiled for three waves per SIMD (168 VGPRs; the few spilled values
+// cost less than the latency the third wave hides), like the FP32 kernel.
 template <int NB, int UPD, bool CORR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CORR ? 1 : 2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CORR ? 1 : 3)))
 void mixed_class_kernel(SolveArgs a) {
   __shared__ Smem<float> sm;
   __shared__ MixedSmem msm;

@@ -47,8 +47,10 @@ namespace {
 // One persistent launch per 16-wide size class: every system of the class has
 // NB blocks, so the kernel holds exactly that class's register footprint. The
 // class is a contiguous range of the size-sorted permutation.
+// FP32 classes are compiled for three waves per SIMD, FP64 classes (twice the
+// tile registers) for two.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
 void solve_class_kernel(SolveArgs a) {
   __shared__ Smem<T> sm;
   block_setup<T>(a, sm);

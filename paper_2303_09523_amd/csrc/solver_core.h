@@ -92,14 +92,16 @@ struct WaveScratch {
   T buf[16 * 17];     // tile transposes and the read-out
 };
 
+// Per-workgroup tables. Every covariance table holds NEGATED values (the
+// factorisation works on S = -M), so an assembled entry needs no sign flip.
 template <typename T> struct Smem {
-  T tc[kTcSize];
-  T t0[kT0Size];
+  T tc[kTcSize];      // -Cov by pair class
+  T t0[kT0Size];      // -c0 by (target, class)
   int sdesc[128];
   WaveScratch<T> ws[kWaves];
 };
-// FP32 blocks also keep the covariance of every candidate pair, so a matrix
-// entry is a single LDS read.
+// FP32 blocks also keep the (negated) covariance of every candidate pair, so a
+// matrix entry is a single LDS read.
 template <> struct Smem<float> {
   float tc[kTcSize];
   float t0[kT0Size];
@@ -126,24 +128,35 @@ __device__ __forceinline__ int pair_class(int dp, int dq) {
   return ((cp ^ cq) & 64) | ((ddy < 0 ? -ddy : ddy) << 3) | (ddx < 0 ? -ddx : ddx);
 }
 
+// -Cov of two data points: FP32 from the pair table (byte offsets of the row
+// and column, see cc_row / cc_col), FP64 from the class table.
 template <typename T>
-__device__ __forceinline__ T cov_pair(int dp, int dq, const Smem<T>& sm, int ncand);
+__device__ __forceinline__ T neg_cov_pair(int dp, int dq, int rbase, int col, const Smem<T>& sm);
 template <>
-__device__ __forceinline__ float cov_pair<float>(int dp, int dq, const Smem<float>& sm, int ncand) {
-  return sm.cc[(dp & 0x7f) * ncand + (dq & 0x7f)];
+__device__ __forceinline__ float neg_cov_pair<float>(int, int, int rbase, int col,
+                                                     const Smem<float>& sm) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(sm.cc) + rbase + col);
 }
 template <>
-__device__ __forceinline__ double cov_pair<double>(int dp, int dq, const Smem<double>& sm, int) {
+__device__ __forceinline__ double neg_cov_pair<double>(int dp, int dq, int, int,
+                                                       const Smem<double>& sm) {
   return sm.tc[pair_class(dp, dq)];
 }
 
-// Entry M[p][q] of the augmented matrix from the two indices' descriptors:
+// Byte offsets of a descriptor's row and column in the FP32 pair table (0 for
+// rows and columns that are not data points, which never read it).
+__device__ __forceinline__ int cc_row(int d, int ncand) {
+  return d >= 0 ? (d & 0x7f) * ncand * (int)sizeof(float) : 0;
+}
+__device__ __forceinline__ int cc_col(int d) { return d >= 0 ? (d & 0x7f) * (int)sizeof(float) : 0; }
+
+// Entry -M[p][q] of the augmented matrix from the two indices' descriptors:
 //   >= 0: data point, -1: identity padding, <= -2: border row b = -2 - d.
 template <typename T>
-__device__ __forceinline__ T entry(int dp, int dq, float vp, float vq, bool same,
-                                   const Smem<T>& sm, int ncand) {
-  if (dp >= 0 && dq >= 0) return cov_pair<T>(dp, dq, sm, ncand);
-  if (dp == -1 || dq == -1) return same ? T(1) : T(0);
+__device__ __forceinline__ T neg_entry(int dp, int dq, int rbase, int col, float vp, float vq,
+                                       bool same, const Smem<T>& sm) {
+  if (dp >= 0 && dq >= 0) return neg_cov_pair<T>(dp, dq, rbase, col, sm);
+  if (dp == -1 || dq == -1) return same ? T(-1) : T(0);
   if (dp < -1 && dq < -1) return T(0);
   int b, d;
   float v;
@@ -152,16 +165,17 @@ __device__ __forceinline__ T entry(int dp, int dq, float vp, float vq, bool same
   } else {
     b = -2 - dq; d = dp; v = vp;
   }
-  if (b == 0) return T(1);
-  if (b == 1) return T(v);
+  if (b == 0) return T(-1);
+  if (b == 1) return T(-v);
   return sm.t0[(b - 2) * kT0Stride + (d >> 16)];
 }
 
 // Pivot of one column: records the range of pivots and replaces a pivot that
-// is not positive and finite by 1 (the system is then flagged).
+// is not positive (NaN included) by 1 (the system is then flagged). Inputs are
+// finite (checked at placement) and scaled, so a pivot cannot overflow.
 template <typename T>
 __device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) {
-  if (!(piv > T(0)) || !isfinite(piv)) {
+  if (!(piv > T(0))) {
     bad = true;
     piv = T(1);
   }
@@ -179,6 +193,19 @@ __device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) 
 // the panel's rank-4 update with one MFMA (and one more for X), instead of
 // four rank-1 MFMAs. Entries above the diagonal are not kept up to date.
 //
+// FP32 pivots are uniform values; positive finite floats order like their bit
+// patterns, so the check and the running range run on the scalar unit.
+__device__ __forceinline__ float take_pivot_bits(float piv, unsigned& minb, unsigned& maxb,
+                                                 bool& bad) {
+  unsigned b = __float_as_uint(piv);
+  const bool ok = (b - 1u) < 0x7f7fffffu;   // 0 < piv < +inf (NaN and -0 excluded)
+  b = ok ? b : 0x3f800000u;                 // 1.0f
+  bad = bad || !ok;
+  minb = b < minb ? b : minb;
+  maxb = b > maxb ? b : maxb;
+  return __uint_as_float(b);
+}
+
 // FP32 layout: the panel's four columns sit in one lane group (elements 0..3),
 // so the in-panel work is lane-local and the MFMA operand (column k of the
 // panel in lane group k) goes through LDS.
@@ -186,6 +213,7 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
                                             float& maxpiv, bool& bad) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
+  unsigned minb = __float_as_uint(minpiv), maxb = __float_as_uint(maxpiv);
 #pragma unroll
   for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
 #pragma unroll
@@ -197,16 +225,19 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
       for (int v0 = 0; v0 < 4; ++v0) {
         const int c = 4 * p + v0;
         if (c < ne) {
-          const float piv = take_pivot(-lane_value(D[v0], 16 * p + c), minpiv, maxpiv, bad);
+          const float piv = take_pivot_bits(-lane_value(D[v0], 16 * p + c), minb, maxb, bad);
           const float is = inv_sqrt(piv);
-          const float l = (r > c) ? -D[v0] * is : 0.0f;   // L[r][c] in the panel's lanes
+          // L[r][c] in the panel's lanes and 0 elsewhere, so the in-panel
+          // updates below leave the other lane groups' columns unchanged
+          const float l = (mine && r > c) ? -D[v0] * is : 0.0f;
           P[v0] = l;
-          X[v0] = mine ? X[v0] * is : X[v0];
+          X[v0] *= mine ? is : 1.0f;
+          const float xm = mine ? X[v0] : 0.0f;
 #pragma unroll
           for (int v1 = v0 + 1; v1 < 4; ++v1) {
             const float s = lane_value(l, 16 * p + 4 * p + v1);   // L[c1][c]
-            D[v1] = mine ? D[v1] + l * s : D[v1];
-            X[v1] = mine ? X[v1] - X[v0] * s : X[v1];
+            D[v1] += l * s;
+            X[v1] -= xm * s;
           }
         } else {
           P[v0] = 0.0f;
@@ -229,6 +260,8 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
       }
     }
   }
+  minpiv = __uint_as_float(minb);
+  maxpiv = __uint_as_float(maxb);
 }
 
 // FP64 layout: the panel's columns 4p+k sit in element p of lane group k, which
@@ -297,13 +330,14 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
   constexpr int N = 16 * NB;
   const int bstart = N - nb;
   V L[NB * (NB + 1) / 2];
-  int rd[NB];
+  int rd[NB], rb[NB];
   float rv[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int p = 16 * i + r;
     rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
     rv[i] = p < n ? ws.val[p] : 0.0f;
+    rb[i] = cc_row(rd[i], ncand);
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -311,13 +345,14 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     // table reads would hold them in registers for the whole factorisation
     __builtin_amdgcn_sched_barrier(0);
     // ---- assemble block column j (negated) ----
-    int cd[4];
+    int cd[4], cb[4];
     float cv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = 16 * j + colmap<T>(g, v);
       cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
       cv[v] = q < n ? ws.val[q] : 0.0f;
+      cb[v] = cc_col(cd[v]);
     }
     const bool colC = 16 * j + 16 <= n;
 #pragma unroll
@@ -325,12 +360,12 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
       V t;
       if (colC && 16 * i + 16 <= n) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) t[v] = -cov_pair<T>(rd[i], cd[v], sm, ncand);
+        for (int v = 0; v < 4; ++v) t[v] = neg_cov_pair<T>(rd[i], cd[v], rb[i], cb[v], sm);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool same = (i == j) && (r == colmap<T>(g, v));
-          t[v] = -entry<T>(rd[i], cd[v], rv[i], cv[v], same, sm, ncand);
+          t[v] = neg_entry<T>(rd[i], cd[v], rb[i], cb[v], rv[i], cv[v], same, sm);
         }
       }
       L[tix(i, j)] = t;
@@ -414,8 +449,8 @@ template <typename T>
 __device__ void init_block(const SolveArgs& a, Smem<T>& sm, double tscale) {
   const double* tcs = a.tab.tc_d;
   const double* t0s = a.tab.t0_d;
-  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) sm.tc[i] = T(tcs[i] * tscale);
-  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(t0s[i] * tscale);
+  for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) sm.tc[i] = T(-(tcs[i] * tscale));
+  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(-(t0s[i] * tscale));
   for (int i = threadIdx.x; i < 128; i += blockDim.x)
     sm.sdesc[i] = i < a.geo.ncand ? cand_desc(i, a.geo.r, a.geo.W, a.geo.W2) : 0;
 }
@@ -493,11 +528,11 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
   init_block<T>(a, sm, tscale);
   __syncthreads();
   if constexpr (sizeof(T) == 4) {
-    // covariance of every candidate pair, rounded once from the FP64 table
+    // (negated) covariance of every candidate pair, rounded once from the FP64 table
     const int nc = a.geo.ncand;
     for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
       const int p = i / nc, q = i - p * nc;
-      sm.cc[i] = (float)(a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale);
+      sm.cc[i] = (float)(-(a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale));
     }
     __syncthreads();
   }
