@@ -127,6 +127,16 @@ def traffic_from_profiles(args):
         return None
 
 
+def class_counts(bucket, nb):
+    """Systems per 16-wide size class NB (n + nb rounded up to 16)."""
+    out = {}
+    for n, c in enumerate(bucket):
+        if c:
+            k = (n + nb + 15) // 16
+            out[k] = out.get(k, 0) + int(c)
+    return {f"NB{k}": v for k, v in sorted(out.items())}
+
+
 DTYPES = {"fp32": "f32", "fp64": "f64", "mixed_fp16": "f16x3+f32", "mixed_bf16": "bf16x3+f32"}
 
 
@@ -397,9 +407,10 @@ def main():
         "loso": loso,
         "calibration": calib,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in pstats["phase_ms"].items()},
-        "solver_stats": {k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
-                                               "n_nonpositive_pivot", "n_not_converged",
-                                               "max_kappa_est")},
+        "solver_stats": dict({k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
+                                                    "n_nonpositive_pivot", "n_not_converged",
+                                                    "max_kappa_est")},
+                             systems_per_size_class=class_counts(stats["bucket"], w.upsample + 1)),
         "host_wall_s": round(t_host, 3),
     }
     print(json.dumps(out))
