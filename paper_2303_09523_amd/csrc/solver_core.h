@@ -99,6 +99,7 @@ template <typename T> struct Smem {
   T t0[kT0Size];      // -c0 by (target, class)
   int sdesc[128];
   WaveScratch<T> ws[kWaves];
+  uint8_t cls[kMaxCand * kMaxCand];   // pair class of every candidate pair
 };
 // FP32 blocks also keep the (negated) covariance of every candidate pair, so a
 // matrix entry is a single LDS read.
@@ -128,8 +129,8 @@ __device__ __forceinline__ int pair_class(int dp, int dq) {
   return ((cp ^ cq) & 64) | ((ddy < 0 ? -ddy : ddy) << 3) | (ddx < 0 ? -ddx : ddx);
 }
 
-// -Cov of two data points: FP32 from the pair table (byte offsets of the row
-// and column, see cc_row / cc_col), FP64 from the class table.
+// -Cov of two data points: FP32 from the pair table, FP64 from the class table
+// through the pair-class byte table (offsets from cc_row / cc_col).
 template <typename T>
 __device__ __forceinline__ T neg_cov_pair(int dp, int dq, int rbase, int col, const Smem<T>& sm);
 template <>
@@ -138,17 +139,20 @@ __device__ __forceinline__ float neg_cov_pair<float>(int, int, int rbase, int co
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(sm.cc) + rbase + col);
 }
 template <>
-__device__ __forceinline__ double neg_cov_pair<double>(int dp, int dq, int, int,
+__device__ __forceinline__ double neg_cov_pair<double>(int, int, int rbase, int col,
                                                        const Smem<double>& sm) {
-  return sm.tc[pair_class(dp, dq)];
+  return sm.tc[sm.cls[rbase + col]];
 }
 
-// Byte offsets of a descriptor's row and column in the FP32 pair table (0 for
-// rows and columns that are not data points, which never read it).
-__device__ __forceinline__ int cc_row(int d, int ncand) {
-  return d >= 0 ? (d & 0x7f) * ncand * (int)sizeof(float) : 0;
+// Offsets of a descriptor's row and column in the pair tables (0 for rows and
+// columns that are not data points, which never read them): bytes into the
+// FP32 covariance table, entries of the FP64 class table.
+template <typename T> __device__ __forceinline__ int cc_row(int d, int ncand) {
+  return d >= 0 ? (d & 0x7f) * ncand * (sizeof(T) == 4 ? 4 : 1) : 0;
 }
-__device__ __forceinline__ int cc_col(int d) { return d >= 0 ? (d & 0x7f) * (int)sizeof(float) : 0; }
+template <typename T> __device__ __forceinline__ int cc_col(int d) {
+  return d >= 0 ? (d & 0x7f) * (sizeof(T) == 4 ? 4 : 1) : 0;
+}
 
 // Entry -M[p][q] of the augmented matrix from the two indices' descriptors:
 //   >= 0: data point, -1: identity padding, <= -2: border row b = -2 - d.
@@ -264,6 +268,23 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
   maxpiv = __uint_as_float(maxb);
 }
 
+// FP64 pivots: the same on the high word (sign, exponent and 20 mantissa bits,
+// enough for the pivot range); a pivot below 2^-1022 counts as non-positive.
+__device__ __forceinline__ double take_pivot_hi(double piv, double& minpiv, double& maxpiv,
+                                                bool& bad) {
+  const long long b = __double_as_longlong(piv);
+  const unsigned hi = (unsigned)(b >> 32);
+  const bool ok = (hi - 1u) < 0x7fefffffu;   // 2^-1022 <= piv < +inf
+  const double p = ok ? piv : 1.0;
+  bad = bad || !ok;
+  const unsigned ph = ok ? hi : 0x3ff00000u;
+  const unsigned mn = (unsigned)(__double_as_longlong(minpiv) >> 32);
+  const unsigned mx = (unsigned)(__double_as_longlong(maxpiv) >> 32);
+  if (ph < mn) minpiv = p;
+  if (ph > mx) maxpiv = p;
+  return p;
+}
+
 // FP64 layout: the panel's columns 4p+k sit in element p of lane group k, which
 // is already the MFMA operand layout. The panel (and the same columns of X) is
 // copied through LDS so that every lane group holds all four columns of its
@@ -292,7 +313,7 @@ __device__ __forceinline__ void diag_factor(f64x4& D, f64x4& X, int ne, double* 
       for (int k0 = 0; k0 < 4; ++k0) {
         const int c = 4 * p + k0;
         if (c < ne) {
-          const double piv = take_pivot(-lane_value(dl[k0], c), minpiv, maxpiv, bad);
+          const double piv = take_pivot_hi(-lane_value(dl[k0], c), minpiv, maxpiv, bad);
           const double is = inv_sqrt(piv);
           const double l = (r > c) ? -dl[k0] * is : 0.0;   // L[r][c]
           dl[k0] = l;
@@ -337,7 +358,7 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     const int p = 16 * i + r;
     rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
     rv[i] = p < n ? ws.val[p] : 0.0f;
-    rb[i] = cc_row(rd[i], ncand);
+    rb[i] = cc_row<T>(rd[i], ncand);
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -352,7 +373,7 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
       const int q = 16 * j + colmap<T>(g, v);
       cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
       cv[v] = q < n ? ws.val[q] : 0.0f;
-      cb[v] = cc_col(cd[v]);
+      cb[v] = cc_col<T>(cd[v]);
     }
     const bool colC = 16 * j + 16 <= n;
 #pragma unroll
@@ -527,6 +548,14 @@ template <typename T>
 __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, double tscale = 1.0) {
   init_block<T>(a, sm, tscale);
   __syncthreads();
+  if constexpr (sizeof(T) == 8) {
+    const int nc = a.geo.ncand;
+    for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
+      const int p = i / nc, q = i - p * nc;
+      sm.cls[i] = (uint8_t)pair_class(sm.sdesc[p], sm.sdesc[q]);
+    }
+    __syncthreads();
+  }
   if constexpr (sizeof(T) == 4) {
     // (negated) covariance of every candidate pair, rounded once from the FP64 table
     const int nc = a.geo.ncand;

@@ -141,7 +141,7 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     const int p = 16 * i + r;
     rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
     rv[i] = p < n ? ws.val[p] : 0.0f;
-    rb[i] = cc_row(rd[i], ncand);
+    rb[i] = cc_row<float>(rd[i], ncand);
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
       const int q = 16 * j + 4 * g + v;
       cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
       cv[v] = q < n ? ws.val[q] : 0.0f;
-      cb[v] = cc_col(cd[v]);
+      cb[v] = cc_col<float>(cd[v]);
     }
     const bool colC = 16 * j + 16 <= n;
     f32x4 S[NB];
