@@ -49,18 +49,19 @@ template <> struct PairStore<0> {
   __device__ __forceinline__ f32x4 get(int h) const { return t[h]; }
 };
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 template <typename E, typename V4, typename V8> struct SplitPair {
+  typedef E V2 __attribute__((ext_vector_type(2)));
   V4 hi[2], lo[2];   // whole 4-element halves; concatenated at each use
+  // hi = round(x), lo = round(x - hi), two elements per packed conversion
   __device__ __forceinline__ void put(int h, const f32x4& x) {
-    V4 vh, vl;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const E e = (E)x[v];
-      vh[v] = e;
-      vl[v] = (E)(x[v] - (float)e);
-    }
-    hi[h] = vh;
-    lo[h] = vl;
+    const f32x2 a = {x[0], x[1]}, b = {x[2], x[3]};
+    const V2 ha = __builtin_convertvector(a, V2), hb = __builtin_convertvector(b, V2);
+    const V2 la = __builtin_convertvector(a - __builtin_convertvector(ha, f32x2), V2);
+    const V2 lb = __builtin_convertvector(b - __builtin_convertvector(hb, f32x2), V2);
+    hi[h] = __builtin_shufflevector(ha, hb, 0, 1, 2, 3);
+    lo[h] = __builtin_shufflevector(la, lb, 0, 1, 2, 3);
   }
   __device__ __forceinline__ f32x4 get(int h) const {
     f32x4 x;
