@@ -360,6 +360,86 @@ def main():
                 "loss_grad_evals_per_s": round(1000.0 / (fms + bms), 2)}
         pl.close()
 
+    # ---- precision study on the ill-conditioned Gaussian workload ----
+    study = None
+    if not args.no_extra:
+        w3 = W.workload("precision_48x384")
+        s3, e3 = W.make_inputs(w3)
+        samp3 = None
+        if not args.no_cpu:
+            _, samp3 = cpu_baseline(w3, s3, e3, 4.0, seed=777)
+        st3 = torch.from_numpy(s3).to(dev)
+        et3 = torch.from_numpy(e3).to(dev)
+        v3 = torch.empty((w3.upsample * (w3.nslices - 1) + 1, w3.m, w3.m), dtype=torch.float32,
+                         device=dev)
+        var3 = torch.empty_like(v3)
+        study = {"workload": w3.name, "variogram": [w3.vario.model, w3.vario.nugget,
+                                                     w3.vario.sill, w3.vario.range],
+                 "kriged_voxels": w3.kriged_voxels, "modes": {}}
+        modes = [("fp32", "fp32", 0, 0.0), ("fp32 + condition routing (1e-5)", "fp32", 0, 1e-5),
+                 ("mixed_fp16 read-out", "mixed_fp16", 0, 0.0),
+                 ("mixed_bf16 read-out", "mixed_bf16", 0, 0.0),
+                 ("mixed_fp16 + fp64 correction", "mixed_fp16", 1, 0.0),
+                 ("mixed_bf16 + fp64 correction", "mixed_bf16", 1, 0.0), ("fp64", "fp64", 0, 0.0)]
+        for name, prec, rmax, tol in modes:
+            pv = P.Plan(w3.m, w3.m, w3.nslices, w3.upsample, w3.radius, 4, prec, "batched",
+                        refine_max=rmax, refine_tol=tol)
+            for _ in range(1):
+                pv.execute(st3, w3.vario, et3, volume=v3, variance=var3)
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record()
+            pv.execute(st3, w3.vario, et3, volume=v3, variance=var3)
+            a1.record()
+            torch.cuda.synchronize()
+            sv = pv.stats()
+            pv.close()
+            ent = {"ms": round(a0.elapsed_time(a1), 3),
+                   "n_fp64_resolved": sv["n_fp64_fallback"], "n_refined": sv["n_refined"],
+                   "n_nonpositive_pivot": sv["n_nonpositive_pivot"],
+                   "max_kappa_est": sv["max_kappa_est"]}
+            if samp3 is not None:
+                idx, est_o, var_o = samp3
+                plane = w3.m * w3.m
+                g, p_ = idx // plane, idx % plane
+                zs = g[:, None] * w3.upsample + np.arange(1, w3.upsample)[None, :]
+                yy, xx = (p_ // w3.m)[:, None], (p_ % w3.m)[:, None]
+                ge = v3[torch.from_numpy(zs).to(dev),
+                        torch.from_numpy(np.broadcast_to(yy, zs.shape).copy()).to(dev),
+                        torch.from_numpy(np.broadcast_to(xx, zs.shape).copy()).to(dev)]
+                ge = ge.double().cpu().numpy()
+                zmax = float(np.abs(s3).max())
+                ee = np.abs(ge - est_o) / np.maximum(np.abs(est_o), 0.01 * zmax)
+                ent.update({"voxels": int(ee.size), "max_rel_err_est": float(ee.max()),
+                            "p9999_rel_err_est": float(np.percentile(ee, 99.99)),
+                            "normwise_est": float(np.abs(ge - est_o).max() / np.abs(est_o).max())})
+            study["modes"][name] = ent
+            print(f"# precision study {name}: {ent}", file=sys.stderr, flush=True)
+
+    # ---- variogram fit: 200 Adam steps on the leave-one-slice-out loss ----
+    fit = None
+    if not args.no_extra:
+        from paper_2303_09523_amd.autograd import fit_variogram
+        wl = W.workload("loso_16x128")
+        sl_, _ = W.make_inputs(wl)
+        slt = torch.from_numpy(sl_).to(dev)
+        pl = P.Plan(wl.m, wl.m, wl.nslices, 2, wl.radius, 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        traj = fit_variogram(pl, slt, (0.1, 1.0, 2.0), steps=200, lr=0.05, model="exponential")
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        pl.close()
+        l0, th0 = traj[0]
+        l1, th1 = traj[-1]
+        fit = {"workload": wl.name, "steps": 200, "seconds": round(tf, 3),
+               "loss_start": l0, "loss_end": l1,
+               "theta_end": [float(x) for x in th1],
+               "nugget_over_sill_end": float(th1[0] / th1[1]), "range_end": float(th1[2]),
+               "truth": {"nugget_over_sill": 0.02 / 0.8, "range": 5.0}}
+        print(f"# fit: {fit}", file=sys.stderr, flush=True)
+
     plain = None
     if not args.no_plain:
         sub = min(w.nslices, 9)
@@ -405,6 +485,8 @@ def main():
         "plain_fp32": plain,
         "batched_variants": others,
         "loso": loso,
+        "variogram_fit": fit,
+        "precision_study": study,
         "calibration": calib,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in pstats["phase_ms"].items()},
         "solver_stats": dict({k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
