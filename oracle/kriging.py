@@ -18,6 +18,12 @@ What it computes, in the paper's order:
   constant predictor q_1 = 1, i.e. ordinary kriging: the bordered system
   [[C, 1], [1^T, 0]] [w; mu] = [c0; 1], solved here with LAPACK (dgesv).
 * The kriging (estimation-error) variance is sill - w^T c0 - mu.
+* With a drift (``drift="linear_z"``) the same Appendix A system is solved with
+  two predictors, q_0 = 1 and q_1 = the point's slice (0 lower, 1 upper; the
+  target's value is t/f): [[C, Q], [Q^T, 0]] [w; phi] = [c0; q0], variance
+  sill - w^T c0 - phi^T q0 (universal kriging with a linear trend across the
+  gap). A system whose kept points all lie in one slice cannot carry that
+  trend (Q loses rank) and is solved as ordinary kriging.
 
 Readings of what the paper leaves open (each is also listed in the design doc):
 
@@ -198,6 +204,24 @@ def bordered_solve(C, c0):
     return sol[:, :n, :], sol[:, n, :]
 
 
+def drift_solve(C, c0, Q, q0):
+    """Solve Appendix A's extended system [[C, Q], [Q^T, 0]] [w; phi] = [c0; q0]
+    (LAPACK dgesv, batched). C [G][n][n], c0 [G][n][T], Q [G][n][p], q0 [G][p][T].
+    Returns (w [G][n][T], phi [G][p][T])."""
+    G, n, _ = C.shape
+    p = Q.shape[2]
+    T = c0.shape[2]
+    K = np.zeros((G, n + p, n + p), dtype=np.float64)
+    K[:, :n, :n] = C
+    K[:, :n, n:] = Q
+    K[:, n:, :n] = np.transpose(Q, (0, 2, 1))
+    rhs = np.empty((G, n + p, T), dtype=np.float64)
+    rhs[:, :n, :] = c0
+    rhs[:, n:, :] = q0
+    sol = np.linalg.solve(K, rhs)
+    return sol[:, :n, :], sol[:, n:, :]
+
+
 def krige_points(pts, vals, targets, model, nugget, sill, a):
     """Kriging of one system given explicit coordinates.
 
@@ -217,13 +241,17 @@ def krige_points(pts, vals, targets, model, nugget, sill, a):
     return est, var, w, mu
 
 
-def _systems(lo, hi, elo, ehi, ys, xs, f, targets_t, r, vario, min_points, chunk=8192):
+def _systems(lo, hi, elo, ehi, ys, xs, f, targets_t, r, vario, min_points, chunk=8192,
+             drift="none"):
     """Kriging of systems whose lower / upper slices are lo[i] / hi[i].
 
     lo, hi: float32 [S][H][W]; elo, ehi: uint8 [S][H][W] or None.
     targets_t: target heights above the lower slice (upper slice at f).
+    drift: "none" (ordinary kriging) or "linear_z" (predictors 1 and slice).
     Returns (est [S][T], var [S][T], n [S], kept [S][2W^2]).
     """
+    if drift not in ("none", "linear_z"):
+        raise ValueError(drift)
     model, nug, sill, a = vario
     S = ys.shape[0]
     H, Wd = lo.shape[1], lo.shape[2]
@@ -257,9 +285,22 @@ def _systems(lo, hi, elo, ehi, ys, xs, f, targets_t, r, vario, min_points, chunk
             C = covariance(model, nug, sill, a, d)
             c0 = covariance(model, nug, sill, a, d0)
             w, mu = bordered_solve(C, c0)
+            v = sill - np.einsum("gnt,gnt->gt", w, c0) - mu
+            if drift == "linear_z":
+                sl_pt = cands[ci][:, :, 2].astype(np.float64)        # 0 lower, 1 upper
+                both = (sl_pt.min(axis=1) == 0) & (sl_pt.max(axis=1) == 1)
+                if both.any():
+                    b = np.nonzero(both)[0]
+                    Q = np.stack([np.ones_like(sl_pt[b]), sl_pt[b]], axis=2)      # [G'][n][2]
+                    q0 = np.stack([np.ones(T), np.asarray(targets_t, float) / f])  # [2][T]
+                    q0 = np.broadcast_to(q0, (len(b), 2, T))
+                    wd, ph = drift_solve(C[b], c0[b], Q, q0)
+                    w = w.copy()
+                    w[b] = wd
+                    v[b] = sill - np.einsum("gnt,gnt->gt", wd, c0[b]) - np.einsum("gpt,gpt->gt", ph, q0)
             z = cv[grp[:, None], ci]                              # [G][n]
             est[c0_ + grp] = np.einsum("gn,gnt->gt", z, w)
-            var[c0_ + grp] = sill - np.einsum("gnt,gnt->gt", w, c0) - mu
+            var[c0_ + grp] = v
     return est, var, ns, kept_all
 
 
@@ -270,7 +311,7 @@ def _vtuple(vario):
 
 
 def krige_volume(slices, edge, f: int, r: int, vario, min_points: int = 4,
-                 gaps: Optional[Sequence[int]] = None):
+                 gaps: Optional[Sequence[int]] = None, drift: str = "none"):
     """Reconstruct the volume [(n-1)f+1][H][W] and its kriging variance.
 
     Known slice s is copied to z = s*f with variance 0; every other voxel
@@ -301,7 +342,8 @@ def krige_volume(slices, edge, f: int, r: int, vario, min_points: int = 4,
         else:
             elo = np.broadcast_to(edge[g], (S, H, Wd))
             ehi = np.broadcast_to(edge[g + 1], (S, H, Wd))
-        e, v, n, _ = _systems(lo, hi, elo, ehi, ys, xs, f, list(range(1, f)), r, vario, min_points)
+        e, v, n, _ = _systems(lo, hi, elo, ehi, ys, xs, f, list(range(1, f)), r, vario, min_points,
+                              drift=drift)
         for t in range(1, f):
             vol[g * f + t] = e[:, t - 1].reshape(H, Wd)
             var[g * f + t] = v[:, t - 1].reshape(H, Wd)
@@ -309,7 +351,8 @@ def krige_volume(slices, edge, f: int, r: int, vario, min_points: int = 4,
     return vol, var, npts
 
 
-def krige_sample(slices, edge, f: int, r: int, vario, gs, ys, xs, min_points: int = 4):
+def krige_sample(slices, edge, f: int, r: int, vario, gs, ys, xs, min_points: int = 4,
+                 drift: str = "none"):
     """Kriging of individual systems (g, y, x): (est [S][f-1], var [S][f-1],
     n [S], kept [S][2(2r+1)^2])."""
     vario = _vtuple(vario)
@@ -321,7 +364,7 @@ def krige_sample(slices, edge, f: int, r: int, vario, gs, ys, xs, min_points: in
     else:
         elo, ehi = edge[gs], edge[gs + 1]
     return _systems(lo, hi, elo, ehi, np.asarray(ys, dtype=np.int64), np.asarray(xs, dtype=np.int64),
-                    f, list(range(1, f)), r, vario, min_points)
+                    f, list(range(1, f)), r, vario, min_points, drift=drift)
 
 
 # ----------------------------------------------------------------------------

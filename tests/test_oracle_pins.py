@@ -370,3 +370,75 @@ def test_adam_first_step_is_signed_lr():
     u0 = np.log([0.5, 2.0, 4.0])
     u1 = np.log(traj[-1][1])
     np.testing.assert_allclose(u1 - u0, [0.05, -0.05, -0.05], rtol=1e-6)
+
+
+# ---- universal kriging with a linear drift across the gap (Appendix A, p = 2) ----
+
+def test_drift_reproduces_linear_trend_exactly():
+    """Predictors 1 and the slice position: a field linear across the gap is
+    reproduced exactly at every target, masked or not (the two unbiasedness
+    constraints sum(w) = 1 and sum(w s_i) = t/f do it); ordinary kriging does
+    not reproduce it in general."""
+    n, H, W_, f, r = 4, 11, 13, 4, 2
+    planes = np.array([0.3 + 0.7 * k for k in range(n)], dtype=np.float32)
+    s = np.broadcast_to(planes[:, None, None], (n, H, W_)).copy()
+    rng = np.random.default_rng(5)
+    e = (rng.random((n, H, W_)) < 0.2).astype(np.uint8)
+    for edge in (None, e):
+        v, var, _ = O.krige_volume(s, edge, f, r, ("exponential", 0.01, 1.0, 6.0),
+                                   drift="linear_z")
+        for g in range(n - 1):
+            for t in range(1, f):
+                exact = float(planes[g]) + (float(planes[g + 1]) - float(planes[g])) * t / f
+                np.testing.assert_allclose(v[g * f + t], exact, rtol=0, atol=1e-12)
+    vo, _, _ = O.krige_volume(s, e, f, r, ("exponential", 0.01, 1.0, 6.0))
+    kz = np.ones(vo.shape[0], bool)
+    kz[::f] = False
+    zexact = np.array([[planes[g] + (planes[g + 1] - planes[g]) * t / f for t in range(1, f)]
+                       for g in range(n - 1)]).ravel()
+    assert np.abs(vo[kz].reshape(-1, H * W_).mean(axis=1) - zexact).max() > 1e-3
+
+
+def test_drift_variance_not_below_ordinary():
+    """An extra unbiasedness constraint can only raise the minimum of the
+    estimation variance: sigma^2(drift) >= sigma^2(ordinary) >= 0."""
+    rng = np.random.default_rng(6)
+    s = rng.normal(size=(3, 9, 10)).astype(np.float32)
+    e = (rng.random(s.shape) < 0.15).astype(np.uint8)
+    for vario in (("spherical", 0.0, 1.0, 4.0), ("gaussian", 0.05, 2.0, 5.0)):
+        _, v0, _ = O.krige_volume(s, e, 3, 2, vario)
+        _, v1, _ = O.krige_volume(s, e, 3, 2, vario, drift="linear_z")
+        kz = np.ones(v0.shape[0], bool)
+        kz[::3] = False
+        assert (v1[kz] >= v0[kz] - 1e-12).all()
+        assert (v0[kz] >= -1e-12).all()
+
+
+def test_drift_solve_brute_force_optimal():
+    """The drift weights minimise Q(w) = w'Cw - 2 w'c0 + sill among weights
+    that satisfy both constraints: moving weight between two points of the
+    same slice keeps the constraints and never lowers Q."""
+    rng = np.random.default_rng(7)
+    pts = np.array([[x, y, s * 2.0] for s in (0, 1) for y in (-1, 0, 1) for x in (-1, 0, 1)], float)
+    pts = pts[rng.permutation(len(pts))[:11]]
+    tgt = np.array([[0.2, -0.1, 0.5]])
+    d = np.linalg.norm(pts[:, None] - pts[None], axis=2)
+    C = O.covariance("exponential", 0.0, 1.0, 5.0, d)
+    c0 = O.covariance("exponential", 0.0, 1.0, 5.0, np.linalg.norm(pts - tgt, axis=1))[:, None]
+    sl = pts[:, 2] / 2.0
+    Q = np.stack([np.ones(len(pts)), sl], axis=1)
+    q0 = np.array([[1.0], [0.25]])
+    w, ph = O.drift_solve(C[None], c0[None], Q[None], q0[None])
+    w = w[0, :, 0]
+    assert abs(w.sum() - 1.0) < 1e-12 and abs(w @ sl - 0.25) < 1e-12
+    Qf = lambda x: x @ C @ x - 2 * x @ c0[:, 0] + 1.0
+    base = Qf(w)
+    for i in range(len(w)):
+        for j in range(len(w)):
+            if i != j and sl[i] == sl[j]:
+                e_ = np.zeros_like(w)
+                e_[i], e_[j] = 1e-3, -1e-3
+                assert Qf(w + e_) >= base - 1e-14
+    # variance formula matches Q at the optimum
+    var = 1.0 - w @ c0[:, 0] - ph[0, :, 0] @ q0[:, 0]
+    assert abs(var - base) < 1e-12
