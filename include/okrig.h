@@ -119,6 +119,14 @@ typedef struct {
                            factorisation, so one step reaches the FP64 result) */
   int32_t strict;       /* 1: OKR_E_NOT_CONVERGED is returned at the next sync if a
                            system met a non-positive pivot in its FP64 re-solve */
+  int32_t drift;        /* 0: ordinary kriging (Appendix A with the constant
+                           predictor). 1: universal kriging with a linear trend
+                           across the gap: Appendix A with the predictors 1 and
+                           the point's slice (0 lower, 1 upper; t/f at target
+                           t). Needs BATCHED and, for MIXED_*, refine_max = 0;
+                           upsample <= 14. Systems always hold points of both
+                           slices (the centres are always kept), so the
+                           extended system is regular. */
 } okr_problem;
 
 typedef struct okr_plan okr_plan;   /* opaque: workspace, tables, launch state */

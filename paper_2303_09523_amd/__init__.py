@@ -46,15 +46,16 @@ class Plan:
     def __init__(self, nx: int, ny: int, nslices: int, upsample: int, radius: int,
                  min_points: int = 4, precision: str = "fp32", algo: str = "batched",
                  refine_tol: float = 0.0, refine_max: int = 1, strict: bool = False,
-                 stream=None):
+                 stream=None, drift: str = "none"):
         torch = _torch()
         lib = load()
         self.shape = (nslices, ny, nx)
         self.upsample = upsample
         self.radius = radius
+        drifts = {"none": 0, "linear_z": 1}
         prob = _lib.Problem(nx, ny, nslices, upsample, radius, min_points,
                             _lib.PRECISIONS[precision], _lib.ALGOS[algo], refine_tol, refine_max,
-                            int(strict))
+                            int(strict), drifts[drift] if isinstance(drift, str) else int(drift))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -36,7 +36,7 @@ class Problem(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nslices", C.c_int32),
                 ("upsample", C.c_int32), ("radius", C.c_int32), ("min_points", C.c_int32),
                 ("precision", C.c_int32), ("algo", C.c_int32), ("refine_tol", C.c_double),
-                ("refine_max", C.c_int32), ("strict", C.c_int32)]
+                ("refine_max", C.c_int32), ("strict", C.c_int32), ("drift", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -154,6 +154,20 @@ okr_status validate_problem(const okr_problem* p, std::string* msg) {
     *msg = "the plain per-voxel kernel is FP32 only";
     return OKR_E_UNSUPPORTED;
   }
+  if (p->drift != 0 && p->drift != 1) {
+    *msg = "drift must be 0 (ordinary kriging) or 1 (slice predictor)";
+    return OKR_E_INVALID_ARG;
+  }
+  if (p->drift && (p->algo != OKR_ALGO_BATCHED ||
+                   ((p->precision == OKR_MIXED_FP16 || p->precision == OKR_MIXED_BF16) &&
+                    p->refine_max > 0))) {
+    *msg = "the slice predictor needs the batched algorithm and, for mixed precisions, refine_max 0";
+    return OKR_E_UNSUPPORTED;
+  }
+  if (p->drift && p->upsample > okr::kMaxUpsample - 1) {
+    *msg = "with the slice predictor upsample must be in 1..14";
+    return OKR_E_SHAPE;
+  }
   if (!(p->refine_tol >= 0.0) || p->refine_max < 0 || p->refine_max > 4) {
     *msg = "refine_tol must be >= 0 and refine_max in 0..4";
     return OKR_E_INVALID_ARG;
@@ -252,7 +266,7 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.tab = tables_of(p);
   a.geo = p->geo;
   a.sill = v->sill;
-  a.nb = p->geo.f + 1;
+  a.nb = p->geo.f + 1 + p->geo.drift;
   a.precision = p->prob.precision;
   a.kappa_limit = 1e300;
   a.refine_kappa = 0.0;
@@ -358,6 +372,7 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
   g.W2 = g.W * g.W;
   g.ncand = 2 * g.W2;
   g.min_points = problem->min_points;
+  g.drift = problem->drift;
   g.plane = (long long)g.nx * g.ny;
   g.nsys = g.plane * (g.nslices > 1 ? g.nslices - 1 : 0);
   build_rule(g.r, &p->rule);
@@ -689,6 +704,8 @@ okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float
   if (!d_slices || !d_loss) return fail(p, OKR_E_INVALID_ARG, "slices and loss are required");
   if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL)
     return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out needs a batched plan");
+  if (p->geo.drift)
+    return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is ordinary kriging (no drift)");
   if (p->geo.f != 2)
     return fail(p, OKR_E_UNSUPPORTED,
                 "leave-one-slice-out uses the upsample-2 geometry (held-out slice half-way)");

@@ -25,6 +25,7 @@ constexpr uint8_t kFlagFloor = 1, kFlagRefined = 2, kFlagFp64 = 4, kFlagBadPivot
 
 struct Geometry {
   int nx, ny, nslices, f, r, W, W2, ncand, min_points;
+  int drift;              // 1: the slice of each point is a second predictor
   long long plane;        // nx * ny
   long long nsys;         // (nslices - 1) * plane
 };

@@ -98,6 +98,7 @@ template <typename T> struct Smem {
   T tc[kTcSize];      // -Cov by pair class
   T t0[kT0Size];      // -c0 by (target, class)
   int sdesc[128];
+  int bz;             // border row of the data values (1, or 2 with the slice predictor)
   WaveScratch<T> ws[kWaves];
   uint8_t cls[kMaxCand * kMaxCand];   // pair class of every candidate pair
 };
@@ -107,6 +108,7 @@ template <> struct Smem<float> {
   float tc[kTcSize];
   float t0[kT0Size];
   int sdesc[128];
+  int bz;
   WaveScratch<float> ws[kWaves];
   float cc[kMaxCand * kMaxCand];
 };
@@ -156,6 +158,9 @@ template <typename T> __device__ __forceinline__ int cc_col(int d) {
 
 // Entry -M[p][q] of the augmented matrix from the two indices' descriptors:
 //   >= 0: data point, -1: identity padding, <= -2: border row b = -2 - d.
+// Border rows: b = 0 the constant predictor, 0 < b < bz the point's slice
+// (0 lower, 1 upper; with the drift), b = bz the data values, b > bz the
+// covariances with target b - bz.
 template <typename T>
 __device__ __forceinline__ T neg_entry(int dp, int dq, int rbase, int col, float vp, float vq,
                                        bool same, const Smem<T>& sm) {
@@ -169,9 +174,38 @@ __device__ __forceinline__ T neg_entry(int dp, int dq, int rbase, int col, float
   } else {
     b = -2 - dq; d = dp; v = vp;
   }
+  const int bz = sm.bz;
   if (b == 0) return T(-1);
-  if (b == 1) return T(-v);
-  return sm.t0[(b - 2) * kT0Stride + (d >> 16)];
+  if (b < bz) return T(-((d >> 14) & 1));
+  if (b == bz) return T(-v);
+  return sm.t0[(b - bz - 1) * kT0Stride + (d >> 16)];
+}
+
+// Estimate and variance of target t (1-based) from the Schur block G = B'C^-1 B
+// left in buf (lower triangle, border rows from ne: 1, [slice], z, c0_1, ...).
+// Ordinary kriging: nu = (G_1t - 1) / G_11. With the slice predictor the two
+// Lagrange multipliers solve G_QQ nu = G_Qt - q0, q0 = (1, t/f). Then
+//   z_hat = G_zt - G_zQ nu,  sigma^2 = sill - G_tt + G_tQ nu - nu' q0.
+template <typename T>
+__device__ __forceinline__ void schur_readout(const T* buf, int ne, int t, int drift, int f, T sill,
+                                              T& est, T& var) {
+  auto G = [&](int i, int j) { return buf[(ne + i) * 17 + ne + j]; };   // i >= j
+  if (!drift) {
+    const T g11 = G(0, 0), g1z = G(1, 0), g1t = G(1 + t, 0), gzt = G(1 + t, 1);
+    const T gtt = G(1 + t, 1 + t);
+    const T m = (T(1) - g1t) / g11;
+    est = gzt + m * g1z;
+    var = sill - gtt + (T(1) - g1t) * m;
+  } else {
+    const int it = 2 + t;
+    const T a = G(0, 0), b = G(1, 0), c = G(1, 1);
+    const T qt = T(t) / T(f);
+    const T r1 = G(it, 0) - T(1), r2 = G(it, 1) - qt;
+    const T det = a * c - b * b;
+    const T n1 = (c * r1 - b * r2) / det, n2 = (a * r2 - b * r1) / det;
+    est = G(it, 2) - G(2, 0) * n1 - G(2, 1) * n2;
+    var = sill - G(it, it) + G(it, 0) * n1 + G(it, 1) * n2 - n1 - n2 * qt;
+  }
 }
 
 // Pivot of one column: records the range of pivots and replaces a pivot that
@@ -436,17 +470,7 @@ __device__ __forceinline__ void solve_system(int n, int nb, const WaveScratch<T>
   factor_system<T, NB>(n, nb, ws, sm, ncand, buf, minpiv, maxpiv, bad);
   const int lane = threadIdx.x & 63;
   const int ne = 16 - nb;
-  if (lane < ntgt) {
-    const int t = lane + 1;
-    const T g11 = buf[ne * 17 + ne];
-    const T g1z = buf[(ne + 1) * 17 + ne];
-    const T g1t = buf[(ne + 1 + t) * 17 + ne];
-    const T gzt = buf[(ne + 1 + t) * 17 + ne + 1];
-    const T gtt = buf[(ne + 1 + t) * 17 + ne + 1 + t];
-    const T m = (T(1) - g1t) / g11;
-    *est = gzt + m * g1z;
-    *var = sill - gtt + (T(1) - g1t) * m;
-  }
+  if (lane < ntgt) schur_readout<T>(buf, ne, lane + 1, sm.bz - 1, ntgt + 1, sill, *est, *var);
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -474,6 +498,7 @@ __device__ void init_block(const SolveArgs& a, Smem<T>& sm, double tscale) {
   for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(-(t0s[i] * tscale));
   for (int i = threadIdx.x; i < 128; i += blockDim.x)
     sm.sdesc[i] = i < a.geo.ncand ? cand_desc(i, a.geo.r, a.geo.W, a.geo.W2) : 0;
+  if (threadIdx.x == 0) sm.bz = 1 + a.geo.drift;
 }
 
 __device__ __forceinline__ void atomic_max_float(unsigned int* addr, float v) {

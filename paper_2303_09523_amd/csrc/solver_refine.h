@@ -424,25 +424,15 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   bad = false;
   factor_keep<NB, UPD>(n, nb, ws, sm, ncand, ws.buf, mn, mxp, bad, Ls, Xs);
   const int ne = 16 - nb;
+  float est_r = 0.0f;
   if (lane < ntgt) {
-    const int t = lane + 1;
-    const float g11 = ws.buf[ne * 17 + ne];
-    const float g1t = ws.buf[(ne + 1 + t) * 17 + ne];
-    const float gtt = ws.buf[(ne + 1 + t) * 17 + ne + 1 + t];
-    const float m = (1.0f - g1t) / g11;
-    *var_out = (float)(sill * (double)(1.0f - gtt + (1.0f - g1t) * m));
+    float var_r;
+    schur_readout<float>(ws.buf, ne, lane + 1, sm.bz - 1, ntgt + 1, 1.0f, est_r, var_r);
+    *var_out = (float)(sill * (double)var_r);
   }
   __builtin_amdgcn_wave_barrier();
   if (!CORR || !((double)mxp > refine_kappa * (double)mn)) {
-    if (lane < ntgt) {
-      const int t = lane + 1;
-      const float g11 = ws.buf[ne * 17 + ne];
-      const float g1z = ws.buf[(ne + 1) * 17 + ne];
-      const float g1t = ws.buf[(ne + 1 + t) * 17 + ne];
-      const float gzt = ws.buf[(ne + 1 + t) * 17 + ne + 1];
-      const float m = (1.0f - g1t) / g11;
-      *est_out = (double)zref + ldexp((double)(gzt + m * g1z), ex);
-    }
+    if (lane < ntgt) *est_out = (double)zref + ldexp((double)est_r, ex);
     if (nu_scale) *nu_scale = ldexp(1.0, ex);
     __builtin_amdgcn_wave_barrier();
     return false;

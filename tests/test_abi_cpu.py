@@ -44,7 +44,7 @@ def test_status_strings(lib):
 def _prob(**kw):
     from paper_2303_09523_amd import _lib
     d = dict(nx=16, ny=16, nslices=4, upsample=2, radius=1, min_points=4, precision=0, algo=0,
-             refine_tol=1e-4, refine_max=1, strict=0)
+             refine_tol=1e-4, refine_max=1, strict=0, drift=0)
     d.update(kw)
     return _lib.Problem(**d)
 
@@ -54,6 +54,8 @@ def _prob(**kw):
     (dict(upsample=16), 2), (dict(radius=4), 2), (dict(radius=-1), 2), (dict(min_points=0), 1),
     (dict(min_points=19), 1), (dict(precision=7), 1), (dict(algo=3), 1),
     (dict(algo=1, precision=1), 6), (dict(refine_max=9), 1), (dict(refine_tol=-1.0), 1),
+    (dict(drift=2), 1), (dict(drift=1, algo=1), 6), (dict(drift=1, precision=1, refine_max=1), 6),
+    (dict(drift=1, algo=2), 6), (dict(drift=1, upsample=15), 2),
     (dict(nx=65535, ny=65535, nslices=3), 2),
 ])
 def test_plan_validation_before_device(lib, kw, code):

@@ -372,3 +372,55 @@ def test_pattern_cache_splits_exactly(case):
             np.testing.assert_array_equal(wp[z][~m], wb[z][~m])
             assert rel_err_est(vp[z][m], v64[z][m].astype(np.float64), zmax).max() <= 1.2e-7
             assert np.abs(wp[z][m] - w64[z][m]).max() <= 1.2e-7 * sill
+
+
+DRIFT_CASES = [CASES[1], CASES[2], CASES[4], CASES[5]]
+
+
+@pytest.mark.parametrize("case", DRIFT_CASES, ids=[c[0] for c in DRIFT_CASES])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "mixed_fp16"])
+def test_drift_vs_oracle(case, precision, oracle_cache):
+    """Universal kriging with the slice predictor (drift = linear_z) against
+    the oracle's Appendix A solve with the same predictors."""
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    key = name + "/drift"
+    if key not in oracle_cache:
+        s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+        vol, var, _ = O.krige_volume(s, e, f, r, (model, nug, sill, rng_),
+                                     min_points=min(4, 2 * (2 * r + 1) ** 2), drift="linear_z")
+        oracle_cache[key] = (s, e, vol, var)
+    s, e, vol_o, var_o = oracle_cache[key]
+    vol, var, _, _ = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision=precision,
+                             min_points=min(4, 2 * (2 * r + 1) ** 2), drift="linear_z",
+                             refine_max=0)
+    np.testing.assert_array_equal(vol[::f], s)
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    zmax = np.abs(s).max()
+    ee = rel_err_est(vol[kz], vol_o[kz], zmax)
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    nw = np.abs(vol[kz].astype(np.float64) - vol_o[kz]).max() / np.abs(vol_o[kz]).max()
+    print(f"case {name} drift {precision}: est {ee.max():.3e} var {ev.max():.3e} normwise {nw:.3e}",
+          flush=True)
+    bar = TOL["fp64"] if precision == "fp64" else TOL["fp32"]
+    assert ee.max() <= bar
+    assert ev.max() <= max(bar, 1e-5)
+    if precision != "fp64":
+        assert nw <= NORMWISE_FP32
+
+
+def test_drift_reproduces_linear_trend_gpu():
+    """A field linear across the gap is reproduced at every target."""
+    n, ny, nx, f, r = 4, 21, 23, 4, 2
+    planes = np.array([0.3 + 0.7 * k for k in range(n)], dtype=np.float32)
+    s = np.broadcast_to(planes[:, None, None], (n, ny, nx)).copy()
+    rng = np.random.default_rng(5)
+    e = (rng.random((n, ny, nx)) < 0.2).astype(np.uint8)
+    for precision, tol in (("fp64", 2e-7), ("fp32", 2e-5), ("mixed_fp16", 2e-5)):
+        vol, _, _, _ = run_gpu(s, e, f, r, ("exponential", 0.01, 1.0, 6.0), precision=precision,
+                               drift="linear_z", refine_max=0)
+        for g in range(n - 1):
+            for t in range(1, f):
+                exact = float(planes[g]) + (float(planes[g + 1]) - float(planes[g])) * t / f
+                assert np.abs(vol[g * f + t] - exact).max() <= tol * max(1.0, abs(exact)), \
+                    (precision, g, t)
