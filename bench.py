@@ -162,8 +162,8 @@ def main():
                     help="after timing, copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding the gaps over GPUs is designed, not implemented)",
               file=sys.stderr)
         sys.exit(2)
 

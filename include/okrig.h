@@ -62,7 +62,7 @@ typedef int32_t okr_status;
 #define OKR_E_NONFINITE       3  /* non-finite known voxel (reported at a sync) */
 #define OKR_E_DEVICE          4  /* a HIP call failed */
 #define OKR_E_OOM             5  /* device or pinned allocation failed */
-#define OKR_E_UNSUPPORTED     6  /* valid request this build does not serve */
+#define OKR_E_UNSUPPORTED     6  /* valid request the library does not serve */
 #define OKR_E_NOT_CONVERGED   7  /* strict mode: a system failed every precision */
 
 typedef enum { OKR_SPHERICAL = 0, OKR_EXPONENTIAL = 1, OKR_GAUSSIAN = 2 } okr_model;

@@ -25,7 +25,7 @@ What it computes, in the paper's order:
   gap). A system whose kept points all lie in one slice cannot carry that
   trend (Q loses rank) and is solved as ordinary kriging.
 
-Readings of what the paper leaves open (each is also listed in the design doc):
+Readings of what the paper leaves open:
 
 * Covariance model: GSLIB convention with practical range a and total sill;
   Cov(0) = sill, Cov(h > 0) = (sill - nugget) * rho(h).
