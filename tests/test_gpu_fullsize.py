@@ -1,0 +1,68 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (autotuned launch shape, graph replay): sampled systems are
+recomputed one by one by the oracle; properties that hold at any size
+(known planes bit-exact, non-negative variance, neighbour-count histogram
+total) are checked on the whole volume."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from _gpu_util import rel_err_est, rel_err_var
+
+pytestmark = pytest.mark.gpu
+
+# (workload, precision, refine_max, per-voxel bar, normwise bar)
+FULL = [
+    ("edge_32x256", "mixed_fp16", 0, 1e-4, 1e-5),
+    ("edge_32x256", "fp32", 0, 1e-4, 1e-5),
+    ("precision_48x384", "mixed_fp16", 1, 1e-4, 1e-5),
+    ("precision_48x384", "fp64", 0, 1.2e-7, 1.2e-7),
+    ("large_160x512", "mixed_fp16", 0, 1e-4, 1e-5),
+    ("large_160x512", "mixed_fp16", 1, 1e-5, 1e-5),
+]
+
+
+@pytest.mark.parametrize("name,precision,refine_max,bar,bar_nw", FULL,
+                         ids=[f"{f[0]}-{f[1]}-r{f[2]}" for f in FULL])
+def test_full_size_sampled(name, precision, refine_max, bar, bar_nw):
+    import torch
+    import paper_2303_09523_amd as P
+    w = W.workload(name)
+    s, e = W.make_inputs(w)
+    print(f"{name} {precision} refine_max={refine_max}", flush=True)
+    st = torch.from_numpy(s).cuda()
+    et = torch.from_numpy(e).cuda() if e is not None else None
+    plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, precision, "batched",
+                  refine_max=refine_max)
+    vol = torch.empty(plan.out_shape(), dtype=torch.float32, device="cuda")
+    var = torch.empty_like(vol)
+    plan.autotune(st, w.vario, et, volume=vol, variance=var)
+    plan.set_graph(True)
+    plan.execute(st, w.vario, et, volume=vol, variance=var)
+    plan.execute(st, w.vario, et, volume=vol, variance=var)
+    stats = plan.stats()
+    plan.close()
+    assert stats["n_systems"] == w.systems and sum(stats["bucket"]) == w.systems
+    assert torch.equal(vol[::w.upsample].cpu(), torch.from_numpy(s))
+    assert (var[::w.upsample] == 0).all()
+    assert (var >= -1e-6 * w.vario.sill).all()
+    rng = np.random.default_rng(2024)
+    idx = np.sort(rng.choice(w.systems, 3000, replace=False))
+    plane = w.m * w.m
+    g, p = idx // plane, idx % plane
+    y, x = p // w.m, p % w.m
+    vario = (w.vario.model, w.vario.nugget, w.vario.sill, w.vario.range)
+    est_o, var_o, _, _ = O.krige_sample(s, e, w.upsample, w.radius, vario, g, y, x)
+    zs = g[:, None] * w.upsample + np.arange(1, w.upsample)[None, :]
+    ys = np.broadcast_to(y[:, None], zs.shape)
+    xs = np.broadcast_to(x[:, None], zs.shape)
+    vn = vol.cpu().numpy()[zs, ys, xs].astype(np.float64)
+    wn = var.cpu().numpy()[zs, ys, xs].astype(np.float64)
+    zmax = float(np.abs(s).max())
+    ee = rel_err_est(vn, est_o, zmax)
+    ev = rel_err_var(wn, var_o, w.vario.sill)
+    nw = np.abs(vn - est_o).max() / np.abs(est_o).max()
+    print(f"  sampled {ee.size} voxels: est {ee.max():.3e} var {ev.max():.3e} normwise {nw:.3e}",
+          flush=True)
+    assert ee.max() <= bar and nw <= bar_nw and ev.max() <= max(bar, 1e-5)
