@@ -79,11 +79,16 @@ void mixed_class_kernel(SolveArgs a) {
       pipe_commit<float>(q, ws, d0, d1);
       if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int n = __popcll(lo) + __popcll(hi);
+      // nb is fixed for the launch; hidden from loop-invariant code motion so that
+      // the tests on it inside the factorisation stay scalar compares per system
+      // instead of lane masks held (and spilled) across the whole loop
+      int nbs = nb;
+      asm volatile("" : "+s"(nbs));
       double est = 0.0;
       float var = 0.0f, mn, mxp;
       bool bad;
       double scale = 1.0;
-      const bool corr = mixed_system<NB, UPD, CORR>(n, nb, ws, sm, mx, msm, ncand, ntgt, a.sill,
+      const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, msm, ncand, ntgt, a.sill,
                                                     a.refine_kappa, &est, &var, mn, mxp, bad,
                                                     nullptr, &scale);
       bool route = false;

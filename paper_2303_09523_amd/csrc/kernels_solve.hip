@@ -89,7 +89,11 @@ void solve_class_kernel(SolveArgs a) {
       const int n = __popcll(lo) + __popcll(hi);
       T est = 0, var = 0, mn, mx;
       bool bad;
-      solve_system<T, NB>(n, nb, ws, sm, ncand, ws.buf, sill, ntgt, &est, &var, mn, mx, bad);
+      // nb is fixed for the launch: kept out of loop-invariant code motion, as in
+      // the mixed kernel, so its tests stay per-system scalar compares
+      int nbs = nb;
+      asm volatile("" : "+s"(nbs));
+      solve_system<T, NB>(n, nbs, ws, sm, ncand, ws.buf, sill, ntgt, &est, &var, mn, mx, bad);
       finish_system<T>(a, 0, sys, cnt, est, var, mn, mx, bad, tally);
     }
   }

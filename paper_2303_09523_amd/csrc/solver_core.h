@@ -6,6 +6,7 @@
 // with MFMA updates, and the Schur read-out.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "okrig_internal.h"
@@ -107,6 +108,8 @@ template <typename T> struct Smem {
 template <> struct Smem<float> {
   float tc[kTcSize];
   float t0[kT0Size];
+  float bt[2 * kT0Stride];   // class-indexed rows of the predictors: -1, -slice
+  float zr[128];             // zeros: the row read by padding rows and the value row
   int sdesc[128];
   int bz;
   WaveScratch<float> ws[kWaves];
@@ -154,6 +157,68 @@ template <typename T> __device__ __forceinline__ int cc_row(int d, int ncand) {
 }
 template <typename T> __device__ __forceinline__ int cc_col(int d) {
   return d >= 0 ? (d & 0x7f) * (sizeof(T) == 4 ? 4 : 1) : 0;
+}
+
+// ---- FP32 entries without branches ----
+// Every row of the augmented matrix reads one LDS row of the block's tables:
+// a data row its row of the pair table cc, a border row a class-indexed row
+// (bt for the constant and slice predictors, t0 for the target covariances),
+// padding rows and the data-value row the zero row zr. A column supplies an
+// offset into either kind of row (cb: candidate, ct: pair class of the target
+// table), and two selects add what no table holds: the column's data value on
+// the value row and the identity of the padding. Only the lower triangle is
+// assembled this way; the factorisation never reads entries above the diagonal.
+constexpr int kOffT0 = offsetof(Smem<float>, t0);
+constexpr int kOffBt = offsetof(Smem<float>, bt);
+constexpr int kOffZr = offsetof(Smem<float>, zr);
+constexpr int kOffCc = offsetof(Smem<float>, cc);
+
+// Byte offset, from the start of the tables, of the row that descriptor d reads
+// (>= 0 data point, -1 padding, <= -2 border row -2 - d).
+__device__ __forceinline__ int f32_row(int d, int ncand, int bz) {
+  if (d >= 0) return kOffCc + (d & 0x7f) * ncand * 4;
+  const int b = -2 - d;
+  if (d == -1 || b == bz) return kOffZr;
+  if (b == 0) return kOffBt;
+  if (b < bz) return kOffBt + 4 * kT0Stride;
+  return kOffT0 + (b - bz - 1) * 4 * kT0Stride;
+}
+
+__device__ __forceinline__ float lds_at(const Smem<float>& sm, int off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(&sm) + off);
+}
+
+// Tile (i, j) of -M in lane-row layout from the rows' offsets rb and the block
+// column's offsets cb / ct and values cv (n data points, border from bstart,
+// data-value row bstart + bz). Border rows all lie in the last block row.
+template <int NB>
+__device__ __forceinline__ f32x4 tile_f32(int i, int j, int n, int bstart, int bz,
+                                          const int (&rb)[NB], const int (&cb)[4],
+                                          const int (&ct)[4], const float (&cv)[4],
+                                          const Smem<float>& sm) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int p = 16 * i + r;
+  const bool pad = p >= n && p < bstart;
+  f32x4 t;
+  if (i < NB - 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = lds_at(sm, rb[i] + cb[v]);
+  } else {
+    const bool by_class = p >= bstart && p != bstart + bz;
+    const bool value_row = p == bstart + bz;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = 16 * j + 4 * g + v;
+      const float x = lds_at(sm, rb[i] + (by_class ? ct[v] : cb[v]));
+      t[v] = q < n ? (value_row ? -cv[v] : x) : 0.0f;
+    }
+  }
+  if (i == j && 16 * i + 16 > n) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = (pad && r == 4 * g + v) ? -1.0f : t[v];
+  }
+  return t;
 }
 
 // Entry -M[p][q] of the augmented matrix from the two indices' descriptors:
@@ -233,14 +298,19 @@ __device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) 
 //
 // FP32 pivots are uniform values; positive finite floats order like their bit
 // patterns, so the check and the running range run on the scalar unit.
-__device__ __forceinline__ float take_pivot_bits(float piv, unsigned& minb, unsigned& maxb,
-                                                 bool& bad) {
-  unsigned b = __float_as_uint(piv);
-  const bool ok = (b - 1u) < 0x7f7fffffu;   // 0 < piv < +inf (NaN and -0 excluded)
-  b = ok ? b : 0x3f800000u;                 // 1.0f
-  bad = bad || !ok;
+// A pivot with bits b is accepted when b - 1 < 0x7f7fffff (0 < piv < +inf; NaN
+// and -0 excluded), so the largest b - 1 seen (chkb) tells whether any failed.
+__device__ __forceinline__ float take_pivot_bits(unsigned b, unsigned& minb, unsigned& maxb,
+                                                 unsigned& chkb) {
+  const unsigned m = b - 1u;
+  chkb = m > chkb ? m : chkb;
+  b = m < 0x7f7fffffu ? b : 0x3f800000u;   // 1.0f
   minb = b < minb ? b : minb;
   maxb = b > maxb ? b : maxb;
+  // Settle the running values here, in scalar registers. Left free, the
+  // compiler sinks these reductions to their single use after the last tile and
+  // keeps every pivot live until then (spilled to VGPR lanes).
+  asm volatile("" : "+s"(minb), "+s"(maxb), "+s"(chkb));
   return __uint_as_float(b);
 }
 
@@ -251,7 +321,10 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
                                             float& maxpiv, bool& bad) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  unsigned minb = __float_as_uint(minpiv), maxb = __float_as_uint(maxpiv);
+  // the range is uniform; say so, for the scalar-register pin in take_pivot_bits
+  unsigned minb = __builtin_amdgcn_readfirstlane(__float_as_uint(minpiv));
+  unsigned maxb = __builtin_amdgcn_readfirstlane(__float_as_uint(maxpiv));
+  unsigned chkb = 0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
 #pragma unroll
@@ -263,7 +336,9 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
       for (int v0 = 0; v0 < 4; ++v0) {
         const int c = 4 * p + v0;
         if (c < ne) {
-          const float piv = take_pivot_bits(-lane_value(D[v0], 16 * p + c), minb, maxb, bad);
+          // pivot -D[c][c]: the sign flip on the bits keeps the check on the scalar unit
+          const unsigned nb = __builtin_amdgcn_readlane(__float_as_uint(D[v0]), 16 * p + c);
+          const float piv = take_pivot_bits(nb ^ 0x80000000u, minb, maxb, chkb);
           const float is = inv_sqrt(piv);
           // L[r][c] in the panel's lanes and 0 elsewhere, so the in-panel
           // updates below leave the other lane groups' columns unchanged
@@ -300,6 +375,7 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
   }
   minpiv = __uint_as_float(minb);
   maxpiv = __uint_as_float(maxb);
+  bad = bad || chkb >= 0x7f7fffffu;
 }
 
 // FP64 pivots: the same on the high word (sign, exponent and 20 mantissa bits,
@@ -385,14 +461,21 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
   constexpr int N = 16 * NB;
   const int bstart = N - nb;
   V L[NB * (NB + 1) / 2];
+  constexpr bool F32 = sizeof(T) == 4;
+  // FP32: row offsets for tile_f32; FP64: descriptors, values and class-table
+  // offsets for neg_entry
   int rd[NB], rb[NB];
   float rv[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int p = 16 * i + r;
     rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
-    rv[i] = p < n ? ws.val[p] : 0.0f;
-    rb[i] = cc_row<T>(rd[i], ncand);
+    if constexpr (F32) {
+      rb[i] = f32_row(rd[i], ncand, sm.bz);
+    } else {
+      rv[i] = p < n ? ws.val[p] : 0.0f;
+      rb[i] = cc_row<T>(rd[i], ncand);
+    }
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -400,20 +483,28 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     // table reads would hold them in registers for the whole factorisation
     __builtin_amdgcn_sched_barrier(0);
     // ---- assemble block column j (negated) ----
-    int cd[4], cb[4];
+    int cd[4], cb[4], ct[4];
     float cv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = 16 * j + colmap<T>(g, v);
       cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
       cv[v] = q < n ? ws.val[q] : 0.0f;
-      cb[v] = cc_col<T>(cd[v]);
+      if constexpr (F32) {
+        const int d = q < n ? cd[v] : 0;
+        cb[v] = (d & 0x7f) * 4;
+        ct[v] = (d >> 16) * 4;
+      } else {
+        cb[v] = cc_col<T>(cd[v]);
+      }
     }
     const bool colC = 16 * j + 16 <= n;
 #pragma unroll
     for (int i = j; i < NB; ++i) {
       V t;
-      if (colC && 16 * i + 16 <= n) {
+      if constexpr (F32) {
+        t = tile_f32<NB>(i, j, n, bstart, sm.bz, rb, cb, ct, cv, sm);
+      } else if (colC && 16 * i + 16 <= n) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) t[v] = neg_cov_pair<T>(rd[i], cd[v], rb[i], cb[v], sm);
       } else {
@@ -496,6 +587,13 @@ __device__ void init_block(const SolveArgs& a, Smem<T>& sm, double tscale) {
   const double* t0s = a.tab.t0_d;
   for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) sm.tc[i] = T(-(tcs[i] * tscale));
   for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(-(t0s[i] * tscale));
+  if constexpr (sizeof(T) == 4) {
+    // constant predictor -1; slice predictor -s, s = 1 for the upper slice
+    // (class indices 16..31)
+    for (int i = threadIdx.x; i < 2 * kT0Stride; i += blockDim.x)
+      sm.bt[i] = (i < kT0Stride || i >= kT0Stride + 16) ? -1.0f : 0.0f;
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) sm.zr[i] = 0.0f;
+  }
   for (int i = threadIdx.x; i < 128; i += blockDim.x)
     sm.sdesc[i] = i < a.geo.ncand ? cand_desc(i, a.geo.r, a.geo.W, a.geo.W2) : 0;
   if (threadIdx.x == 0) sm.bz = 1 + a.geo.drift;

@@ -135,42 +135,29 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
   const int r = lane & 15, g = lane >> 4;
   constexpr int N = 16 * NB;
   const int bstart = N - nb;
-  int rd[NB], rb[NB];
-  float rv[NB];
+  const int bz = sm.bz;
+  int rb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int p = 16 * i + r;
-    rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
-    rv[i] = p < n ? ws.val[p] : 0.0f;
-    rb[i] = cc_row<float>(rd[i], ncand);
+    rb[i] = f32_row(p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart)), ncand, bz);
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     __builtin_amdgcn_sched_barrier(0);
-    int cd[4], cb[4];
+    int cb[4], ct[4];
     float cv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = 16 * j + 4 * g + v;
-      cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
+      const int d = q < n ? ws.desc[q] : 0;
       cv[v] = q < n ? ws.val[q] : 0.0f;
-      cb[v] = cc_col<float>(cd[v]);
+      cb[v] = (d & 0x7f) * 4;
+      ct[v] = (d >> 16) * 4;
     }
-    const bool colC = 16 * j + 16 <= n;
     f32x4 S[NB];
 #pragma unroll
-    for (int i = j; i < NB; ++i) {
-      if (colC && 16 * i + 16 <= n) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) S[i][v] = neg_cov_pair<float>(rd[i], cd[v], rb[i], cb[v], sm);
-      } else {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool same = (i == j) && (r == 4 * g + v);
-          S[i][v] = neg_entry<float>(rd[i], cd[v], rb[i], cb[v], rv[i], cv[v], same, sm);
-        }
-      }
-    }
+    for (int i = j; i < NB; ++i) S[i] = tile_f32<NB>(i, j, n, bstart, bz, rb, cb, ct, cv, sm);
     // updates from the finished block columns, two at a time
 #pragma unroll
     for (int m = 0; 2 * m + 1 < j; ++m) {
