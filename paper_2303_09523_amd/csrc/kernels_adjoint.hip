@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
     for (int k = 0; k < nk; ++k) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
-      pipe_commit<float>(q, ws, d0, d1);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int n = __popcll(lo) + __popcll(hi);
+      pipe_commit<float>(q, ws, d0, d1, n);
+      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       double est = 0.0, zscale = 1.0;
       float var = 0.0f, mn, mxp;
       bool bad;

@@ -76,9 +76,9 @@ void mixed_class_kernel(SolveArgs a) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
       const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
-      pipe_commit<float>(q, ws, d0, d1);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int n = __popcll(lo) + __popcll(hi);
+      pipe_commit<float>(q, ws, d0, d1, n);
+      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       // nb is fixed for the launch; hidden from loop-invariant code motion so that
       // the tests on it inside the factorisation stay scalar compares per system
       // instead of lane masks held (and spilled) across the whole loop

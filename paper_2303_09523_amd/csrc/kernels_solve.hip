@@ -84,9 +84,9 @@ void solve_class_kernel(SolveArgs a) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
       const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
-      pipe_commit<T>(q, ws, d0, d1);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int n = __popcll(lo) + __popcll(hi);
+      pipe_commit<T>(q, ws, d0, d1, n);
+      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       T est = 0, var = 0, mn, mx;
       bool bad;
       // nb is fixed for the launch: kept out of loop-invariant code motion, as in
@@ -127,9 +127,9 @@ __global__ __launch_bounds__(256) void solve_list_kernel(SolveArgs a) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
       const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
-      pipe_commit<T>(q, ws, d0, d1);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int n = __popcll(lo) + __popcll(hi);
+      pipe_commit<T>(q, ws, d0, d1, n);
+      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
       const int NB = (n + a.nb + 15) >> 4;
       T est = 0, var = 0, mn, mx;
       bool bad;

@@ -89,9 +89,14 @@ constexpr int kChunk = 16;
 template <typename T>
 struct WaveScratch {
   int desc[128];      // point descriptors in system order
-  float val[128];     // point values
+  float val[128];     // point values (0 past the last point)
+  int ofs[128];       // FP32 assembly: pair-table offset | class-table offset << 16
   T buf[16 * 17];     // tile transposes and the read-out
 };
+
+// FP32 class-indexed rows (predictors, target covariances) hold the 32 pair
+// classes and a zero at index 32, which columns that are not data points read.
+constexpr int kT0StrideF = kT0Stride + 1;
 
 // Per-workgroup tables. Every covariance table holds NEGATED values (the
 // factorisation works on S = -M), so an assembled entry needs no sign flip.
@@ -107,8 +112,8 @@ template <typename T> struct Smem {
 // matrix entry is a single LDS read.
 template <> struct Smem<float> {
   float tc[kTcSize];
-  float t0[kT0Size];
-  float bt[2 * kT0Stride];   // class-indexed rows of the predictors: -1, -slice
+  float t0[kMaxUpsample * kT0StrideF];
+  float bt[2 * kT0StrideF];  // class-indexed rows of the predictors: -1, -slice
   float zr[128];             // zeros: the row read by padding rows and the value row
   int sdesc[128];
   int bz;
@@ -164,57 +169,71 @@ template <typename T> __device__ __forceinline__ int cc_col(int d) {
 // a data row its row of the pair table cc, a border row a class-indexed row
 // (bt for the constant and slice predictors, t0 for the target covariances),
 // padding rows and the data-value row the zero row zr. A column supplies an
-// offset into either kind of row (cb: candidate, ct: pair class of the target
-// table), and two selects add what no table holds: the column's data value on
-// the value row and the identity of the padding. Only the lower triangle is
-// assembled this way; the factorisation never reads entries above the diagonal.
+// offset into either kind of row (ofs: candidate in the low half, pair class
+// in the high half; columns past the last point select the zero of the class
+// rows), and the value row adds the column's data value. Only the lower
+// triangle is assembled this way; the factorisation never reads entries above
+// the diagonal.
 constexpr int kOffT0 = offsetof(Smem<float>, t0);
 constexpr int kOffBt = offsetof(Smem<float>, bt);
 constexpr int kOffZr = offsetof(Smem<float>, zr);
 constexpr int kOffCc = offsetof(Smem<float>, cc);
+constexpr int kTailOfs = (4 * kT0Stride) << 16;
 
-// Byte offset, from the start of the tables, of the row that descriptor d reads
-// (>= 0 data point, -1 padding, <= -2 border row -2 - d).
-__device__ __forceinline__ int f32_row(int d, int ncand, int bz) {
-  if (d >= 0) return kOffCc + (d & 0x7f) * ncand * 4;
-  const int b = -2 - d;
-  if (d == -1 || b == bz) return kOffZr;
-  if (b == 0) return kOffBt;
-  if (b < bz) return kOffBt + 4 * kT0Stride;
-  return kOffT0 + (b - bz - 1) * 4 * kT0Stride;
+// Column offsets of a candidate descriptor (bits 0..6 candidate, 16..20 class).
+__device__ __forceinline__ int f32_ofs(int d) {
+  return ((d & 0x7f) << 2) | (((d >> 16) & 31) << 18);
 }
 
 __device__ __forceinline__ float lds_at(const Smem<float>& sm, int off) {
   return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(&sm) + off);
 }
 
-// Tile (i, j) of -M in lane-row layout from the rows' offsets rb and the block
-// column's offsets cb / ct and values cv (n data points, border from bstart,
-// data-value row bstart + bz). Border rows all lie in the last block row.
+// Row offsets of one system: rb[i] for the lane's row in block i; for the last
+// block also the half of ofs the row uses (sh) and whether it is the value row.
 template <int NB>
-__device__ __forceinline__ f32x4 tile_f32(int i, int j, int n, int bstart, int bz,
-                                          const int (&rb)[NB], const int (&cb)[4],
-                                          const int (&ct)[4], const float (&cv)[4],
-                                          const Smem<float>& sm) {
+__device__ __forceinline__ void f32_rows(int n, int bstart, int bz, int ncand,
+                                         const WaveScratch<float>& ws, int (&rb)[NB], int& sh,
+                                         float& vrow) {
+  const int r = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < NB - 1; ++i) {   // data or padding (border rows are in the last block)
+    const int p = 16 * i + r;
+    rb[i] = p < n ? kOffCc + (ws.ofs[p] & 0xffff) * ncand : kOffZr;
+  }
+  const int p = 16 * (NB - 1) + r;
+  const int b = p - bstart;
+  int o;
+  if (p < n) o = kOffCc + (ws.ofs[p] & 0xffff) * ncand;
+  else if (b < 0 || b == bz) o = kOffZr;
+  else if (b == 0) o = kOffBt;
+  else if (b < bz) o = kOffBt + 4 * kT0StrideF;
+  else o = kOffT0 + (b - bz - 1) * 4 * kT0StrideF;
+  rb[NB - 1] = o;
+  sh = (b >= 0 && b != bz) ? 16 : 0;
+  vrow = b == bz ? 1.0f : 0.0f;
+}
+
+// Tile (i, j) of -M in lane-row layout from the row offsets and the block
+// column's offsets ofs and values cv (n data points, border from bstart).
+template <int NB>
+__device__ __forceinline__ f32x4 tile_f32(int i, int j, int n, int bstart, const int (&rb)[NB],
+                                          int sh, float vrow, const int (&ofs)[4],
+                                          const float (&cv)[4], const Smem<float>& sm) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int p = 16 * i + r;
-  const bool pad = p >= n && p < bstart;
   f32x4 t;
   if (i < NB - 1) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) t[v] = lds_at(sm, rb[i] + cb[v]);
+    for (int v = 0; v < 4; ++v) t[v] = lds_at(sm, rb[i] + (ofs[v] & 0xffff));
   } else {
-    const bool by_class = p >= bstart && p != bstart + bz;
-    const bool value_row = p == bstart + bz;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int q = 16 * j + 4 * g + v;
-      const float x = lds_at(sm, rb[i] + (by_class ? ct[v] : cb[v]));
-      t[v] = q < n ? (value_row ? -cv[v] : x) : 0.0f;
-    }
+    for (int v = 0; v < 4; ++v)
+      t[v] = fmaf(vrow, -cv[v], lds_at(sm, rb[i] + (int)__builtin_amdgcn_ubfe(ofs[v], sh, 16)));
   }
   if (i == j && 16 * i + 16 > n) {
+    const int p = 16 * i + r;
+    const bool pad = p >= n && p < bstart;
 #pragma unroll
     for (int v = 0; v < 4; ++v) t[v] = (pad && r == 4 * g + v) ? -1.0f : t[v];
   }
@@ -466,13 +485,15 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
   // offsets for neg_entry
   int rd[NB], rb[NB];
   float rv[NB];
+  int sh = 0;
+  float vrow = 0.0f;
+  if constexpr (F32) {
+    f32_rows<NB>(n, bstart, sm.bz, ncand, ws, rb, sh, vrow);
+  } else {
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int p = 16 * i + r;
-    rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
-    if constexpr (F32) {
-      rb[i] = f32_row(rd[i], ncand, sm.bz);
-    } else {
+    for (int i = 0; i < NB; ++i) {
+      const int p = 16 * i + r;
+      rd[i] = p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart));
       rv[i] = p < n ? ws.val[p] : 0.0f;
       rb[i] = cc_row<T>(rd[i], ncand);
     }
@@ -483,18 +504,17 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     // table reads would hold them in registers for the whole factorisation
     __builtin_amdgcn_sched_barrier(0);
     // ---- assemble block column j (negated) ----
-    int cd[4], cb[4], ct[4];
+    int cd[4], cb[4], ofs[4];
     float cv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = 16 * j + colmap<T>(g, v);
-      cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
-      cv[v] = q < n ? ws.val[q] : 0.0f;
       if constexpr (F32) {
-        const int d = q < n ? cd[v] : 0;
-        cb[v] = (d & 0x7f) * 4;
-        ct[v] = (d >> 16) * 4;
+        ofs[v] = ws.ofs[q];
+        cv[v] = ws.val[q];
       } else {
+        cd[v] = q < n ? ws.desc[q] : (q < bstart ? -1 : -2 - (q - bstart));
+        cv[v] = q < n ? ws.val[q] : 0.0f;
         cb[v] = cc_col<T>(cd[v]);
       }
     }
@@ -503,7 +523,7 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     for (int i = j; i < NB; ++i) {
       V t;
       if constexpr (F32) {
-        t = tile_f32<NB>(i, j, n, bstart, sm.bz, rb, cb, ct, cv, sm);
+        t = tile_f32<NB>(i, j, n, bstart, rb, sh, vrow, ofs, cv, sm);
       } else if (colC && 16 * i + 16 <= n) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) t[v] = neg_cov_pair<T>(rd[i], cd[v], rb[i], cb[v], sm);
@@ -586,13 +606,21 @@ __device__ void init_block(const SolveArgs& a, Smem<T>& sm, double tscale) {
   const double* tcs = a.tab.tc_d;
   const double* t0s = a.tab.t0_d;
   for (int i = threadIdx.x; i < kTcSize; i += blockDim.x) sm.tc[i] = T(-(tcs[i] * tscale));
-  for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(-(t0s[i] * tscale));
   if constexpr (sizeof(T) == 4) {
-    // constant predictor -1; slice predictor -s, s = 1 for the upper slice
-    // (class indices 16..31)
-    for (int i = threadIdx.x; i < 2 * kT0Stride; i += blockDim.x)
-      sm.bt[i] = (i < kT0Stride || i >= kT0Stride + 16) ? -1.0f : 0.0f;
+    // class-indexed rows with a trailing zero: the targets' covariances, the
+    // constant predictor -1 and the slice predictor -s (s = 1 for the upper
+    // slice, class indices 16..31)
+    for (int i = threadIdx.x; i < kMaxUpsample * kT0StrideF; i += blockDim.x) {
+      const int t = i / kT0StrideF, c = i - t * kT0StrideF;
+      sm.t0[i] = c < kT0Stride ? (float)(-(t0s[t * kT0Stride + c] * tscale)) : 0.0f;
+    }
+    for (int i = threadIdx.x; i < 2 * kT0StrideF; i += blockDim.x) {
+      const int c = i < kT0StrideF ? i : i - kT0StrideF;
+      sm.bt[i] = c == kT0Stride ? 0.0f : ((i < kT0StrideF || c >= 16) ? -1.0f : 0.0f);
+    }
     for (int i = threadIdx.x; i < 128; i += blockDim.x) sm.zr[i] = 0.0f;
+  } else {
+    for (int i = threadIdx.x; i < kT0Size; i += blockDim.x) sm.t0[i] = T(-(t0s[i] * tscale));
   }
   for (int i = threadIdx.x; i < 128; i += blockDim.x)
     sm.sdesc[i] = i < a.geo.ncand ? cand_desc(i, a.geo.r, a.geo.W, a.geo.W2) : 0;
@@ -652,15 +680,29 @@ __device__ __forceinline__ void pipe_prefetch(Pipe& q, const SolveArgs& a, int k
   }
 }
 
+// Writes the system's points (n of them) in system order; the slots past the
+// last point get value 0 and the column offsets of a non-point.
 template <typename T>
-__device__ __forceinline__ void pipe_commit(const Pipe& q, WaveScratch<T>& ws, int d0, int d1) {
+__device__ __forceinline__ void pipe_commit(const Pipe& q, WaveScratch<T>& ws, int d0, int d1,
+                                            int n) {
+  const int lane = threadIdx.x & 63;
   if (q.pp0 >= 0) {
     ws.desc[q.pp0] = d0;
     ws.val[q.pp0] = q.pv0;
+    ws.ofs[q.pp0] = f32_ofs(d0);
   }
   if (q.pp1 >= 0) {
     ws.desc[q.pp1] = d1;
     ws.val[q.pp1] = q.pv1;
+    ws.ofs[q.pp1] = f32_ofs(d1);
+  }
+  if (lane >= n) {
+    ws.val[lane] = 0.0f;
+    ws.ofs[lane] = kTailOfs;
+  }
+  if (lane + 64 >= n) {
+    ws.val[lane + 64] = 0.0f;
+    ws.ofs[lane + 64] = kTailOfs;
   }
   __builtin_amdgcn_wave_barrier();
 }

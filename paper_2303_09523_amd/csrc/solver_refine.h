@@ -135,29 +135,23 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
   const int r = lane & 15, g = lane >> 4;
   constexpr int N = 16 * NB;
   const int bstart = N - nb;
-  const int bz = sm.bz;
-  int rb[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) {
-    const int p = 16 * i + r;
-    rb[i] = f32_row(p < n ? ws.desc[p] : (p < bstart ? -1 : -2 - (p - bstart)), ncand, bz);
-  }
+  int rb[NB], sh;
+  float vrow;
+  f32_rows<NB>(n, bstart, sm.bz, ncand, ws, rb, sh, vrow);
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     __builtin_amdgcn_sched_barrier(0);
-    int cb[4], ct[4];
+    int ofs[4];
     float cv[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = 16 * j + 4 * g + v;
-      const int d = q < n ? ws.desc[q] : 0;
-      cv[v] = q < n ? ws.val[q] : 0.0f;
-      cb[v] = (d & 0x7f) * 4;
-      ct[v] = (d >> 16) * 4;
+      ofs[v] = ws.ofs[q];
+      cv[v] = ws.val[q];
     }
     f32x4 S[NB];
 #pragma unroll
-    for (int i = j; i < NB; ++i) S[i] = tile_f32<NB>(i, j, n, bstart, bz, rb, cb, ct, cv, sm);
+    for (int i = j; i < NB; ++i) S[i] = tile_f32<NB>(i, j, n, bstart, rb, sh, vrow, ofs, cv, sm);
     // updates from the finished block columns, two at a time
 #pragma unroll
     for (int m = 0; 2 * m + 1 < j; ++m) {
