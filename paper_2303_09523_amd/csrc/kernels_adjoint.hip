@@ -28,6 +28,8 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   __shared__ Smem<float> sm;
   __shared__ LosoSmem msm;
   __shared__ AdjSmem as;
+  __shared__ WaveScratch<float> wsa[4];
+  __shared__ MixedScratch msa[4];
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
@@ -39,8 +41,8 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   }
   __syncthreads();
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveScratch<float>& ws = sm.ws[wid];
-  MixedScratch& mx = msm.ms[wid];
+  WaveScratch<float>& ws = wsa[wid];
+  MixedScratch& mx = msa[wid];
   double* wv = as.w[wid];
   const int nb = a.nb;
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;

@@ -32,21 +32,30 @@ namespace {
 
 constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;   // 2^-24
 
-// Without the correction the kernel holds only the factorisation's live tiles
-// and is compiled for three waves per SIMD (168 VGPRs; the few spilled values
-// cost less than the latency the third wave hides), like the FP32 kernel.
+// Without the correction the kernel holds only the factorisation's live tiles;
+// it runs eight waves per workgroup, which share one copy of the block tables,
+// so that two workgroups fit a CU's LDS and each SIMD holds four waves (128
+// VGPRs; the few values spilled at NB >= 7 cost less than the latency the
+// fourth wave hides). The corrected form keeps every L tile and runs one wave
+// per SIMD in workgroups of four.
+template <bool CORR> constexpr int mixed_waves() { return CORR ? 4 : 8; }
+
 template <int NB, int UPD, bool CORR>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CORR ? 1 : 3)))
+__global__ __launch_bounds__(64 * mixed_waves<CORR>())
+__attribute__((amdgpu_waves_per_eu(CORR ? 1 : 4)))
 void mixed_class_kernel(SolveArgs a) {
+  constexpr int W = mixed_waves<CORR>();
   __shared__ Smem<float> sm;
   __shared__ MixedSmem msm;
+  __shared__ WaveScratch<float> wsa[W];
+  __shared__ MixedScratch msa[W];
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
   __syncthreads();
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveScratch<float>& ws = sm.ws[wid];
-  MixedScratch& mx = msm.ms[wid];
+  WaveScratch<float>& ws = wsa[wid];
+  MixedScratch& mx = msa[wid];
   const int nb = a.nb;
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
   if (nlo < 1) nlo = 1;
@@ -115,7 +124,8 @@ hipError_t launch_mixed_classes(const SolveArgs& a, int grid, hipStream_t s) {
   const int nbmax = (a.geo.ncand + a.nb + 15) / 16;
 #define OKR_CLS(K)                                                                            \
   if (nbmax >= K) {                                                                           \
-    hipLaunchKernelGGL((mixed_class_kernel<K, UPD, CORR>), dim3(grid), dim3(256), 0, s, a);   \
+    hipLaunchKernelGGL((mixed_class_kernel<K, UPD, CORR>), dim3(grid),                         \
+                       dim3(64 * mixed_waves<CORR>()), 0, s, a);                              \
     hipError_t e = hipGetLastError();                                                         \
     if (e != hipSuccess) return e;                                                            \
   }

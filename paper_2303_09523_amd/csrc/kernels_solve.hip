@@ -53,9 +53,10 @@ template <typename T, int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
 void solve_class_kernel(SolveArgs a) {
   __shared__ Smem<T> sm;
+  __shared__ WaveScratch<T> wsa[4];
   block_setup<T>(a, sm);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveScratch<T>& ws = sm.ws[wid];
+  WaveScratch<T>& ws = wsa[wid];
   const int nb = a.nb;
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
   if (nlo < 1) nlo = 1;
@@ -104,9 +105,10 @@ void solve_class_kernel(SolveArgs a) {
 template <typename T, int NBMAX>
 __global__ __launch_bounds__(256) void solve_list_kernel(SolveArgs a) {
   __shared__ Smem<T> sm;
+  __shared__ WaveScratch<T> wsa[4];
   block_setup<T>(a, sm);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveScratch<T>& ws = sm.ws[wid];
+  WaveScratch<T>& ws = wsa[wid];
   const unsigned long long total = a.ctr->n_fallback_list;
   const T sill = T(a.sill);
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;

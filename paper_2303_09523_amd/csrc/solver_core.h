@@ -83,7 +83,6 @@ template <typename T> __device__ __forceinline__ constexpr int colelem(int c) {
   return sizeof(T) == 4 ? (c & 3) : (c >> 2);
 }
 
-constexpr int kWaves = 4;
 constexpr int kChunk = 16;
 
 template <typename T>
@@ -98,14 +97,14 @@ struct WaveScratch {
 // classes and a zero at index 32, which columns that are not data points read.
 constexpr int kT0StrideF = kT0Stride + 1;
 
-// Per-workgroup tables. Every covariance table holds NEGATED values (the
-// factorisation works on S = -M), so an assembled entry needs no sign flip.
+// Per-workgroup tables (each kernel declares its waves' WaveScratch beside
+// them). Every covariance table holds NEGATED values (the factorisation works
+// on S = -M), so an assembled entry needs no sign flip.
 template <typename T> struct Smem {
   T tc[kTcSize];      // -Cov by pair class
   T t0[kT0Size];      // -c0 by (target, class)
   int sdesc[128];
   int bz;             // border row of the data values (1, or 2 with the slice predictor)
-  WaveScratch<T> ws[kWaves];
   uint8_t cls[kMaxCand * kMaxCand];   // pair class of every candidate pair
 };
 // FP32 blocks also keep the (negated) covariance of every candidate pair, so a
@@ -117,7 +116,6 @@ template <> struct Smem<float> {
   float zr[128];             // zeros: the row read by padding rows and the value row
   int sdesc[128];
   int bz;
-  WaveScratch<float> ws[kWaves];
   float cc[kMaxCand * kMaxCand];
 };
 

@@ -292,7 +292,6 @@ struct MixedScratch {
 struct MixedTables {
   double tc64[kTcSize];
   double t064[kT0Size];
-  MixedScratch ms[4];
 };
 
 // Refined estimates: the FP64 covariance of every candidate pair, so an entry
