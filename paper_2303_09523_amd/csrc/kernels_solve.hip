@@ -47,13 +47,17 @@ namespace {
 // One persistent launch per 16-wide size class: every system of the class has
 // NB blocks, so the kernel holds exactly that class's register footprint. The
 // class is a contiguous range of the size-sorted permutation.
-// FP32 classes are compiled for three waves per SIMD, FP64 classes (twice the
-// tile registers) for two.
+// FP32 classes run eight waves per workgroup sharing one copy of the block
+// tables (two workgroups per CU, four waves per SIMD at 128 VGPRs); FP64
+// classes (twice the tile registers) run two waves per SIMD in workgroups of four.
+template <typename T> constexpr int class_waves() { return sizeof(T) == 4 ? 8 : 4; }
+
 template <typename T, int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2)))
+__global__ __launch_bounds__(64 * class_waves<T>())
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 void solve_class_kernel(SolveArgs a) {
   __shared__ Smem<T> sm;
-  __shared__ WaveScratch<T> wsa[4];
+  __shared__ WaveScratch<T> wsa[class_waves<T>()];
   block_setup<T>(a, sm);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveScratch<T>& ws = wsa[wid];
@@ -147,7 +151,8 @@ hipError_t launch_classes(const SolveArgs& a, int grid, hipStream_t s) {
   const int nbmax = (a.geo.ncand + a.nb + 15) / 16;
 #define OKR_CLS(K)                                                                          \
   if (nbmax >= K) {                                                                         \
-    hipLaunchKernelGGL((solve_class_kernel<T, K>), dim3(grid), dim3(256), 0, s, a);         \
+    hipLaunchKernelGGL((solve_class_kernel<T, K>), dim3(grid), dim3(64 * class_waves<T>()), \
+                       0, s, a);                                                            \
     hipError_t e = hipGetLastError();                                                       \
     if (e != hipSuccess) return e;                                                          \
   }

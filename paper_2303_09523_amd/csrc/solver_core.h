@@ -333,17 +333,20 @@ __device__ __forceinline__ float take_pivot_bits(unsigned b, unsigned& minb, uns
 
 // FP32 layout: the panel's four columns sit in one lane group (elements 0..3),
 // so the in-panel work is lane-local and the MFMA operand (column k of the
-// panel in lane group k) goes through LDS.
+// panel in lane group k) goes through LDS. With want_x false (the last tile
+// of a read-out, whose L^{-T} nothing uses) X is left untouched.
 __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* buf, float& minpiv,
-                                            float& maxpiv, bool& bad) {
+                                            float& maxpiv, bool& bad, bool want_x = true) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   // the range is uniform; say so, for the scalar-register pin in take_pivot_bits
   unsigned minb = __builtin_amdgcn_readfirstlane(__float_as_uint(minpiv));
   unsigned maxb = __builtin_amdgcn_readfirstlane(__float_as_uint(maxpiv));
   unsigned chkb = 0;
+  if (want_x) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
+    for (int v = 0; v < 4; ++v) X[v] = (r == 4 * g + v) ? 1.0f : 0.0f;
+  }
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     if (4 * p < ne) {
@@ -357,17 +360,22 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
           const unsigned nb = __builtin_amdgcn_readlane(__float_as_uint(D[v0]), 16 * p + c);
           const float piv = take_pivot_bits(nb ^ 0x80000000u, minb, maxb, chkb);
           const float is = inv_sqrt(piv);
-          // L[r][c] in the panel's lanes and 0 elsewhere, so the in-panel
-          // updates below leave the other lane groups' columns unchanged
-          const float l = (mine && r > c) ? -D[v0] * is : 0.0f;
+          // column c of L in the panel's lanes, 0 elsewhere, so the in-panel
+          // updates below leave the other lane groups' columns unchanged. Rows
+          // r <= c hold no L entry: what they get only reaches entries above
+          // the diagonal, and the MFMA operand masks them.
+          const float l = mine ? -D[v0] * is : 0.0f;
           P[v0] = l;
-          X[v0] *= mine ? is : 1.0f;
-          const float xm = mine ? X[v0] : 0.0f;
+          float xm = 0.0f;
+          if (want_x) {
+            X[v0] *= mine ? is : 1.0f;
+            xm = mine ? X[v0] : 0.0f;
+          }
 #pragma unroll
           for (int v1 = v0 + 1; v1 < 4; ++v1) {
             const float s = lane_value(l, 16 * p + 4 * p + v1);   // L[c1][c]
             D[v1] += l * s;
-            X[v1] -= xm * s;
+            if (want_x) X[v1] -= xm * s;
           }
         } else {
           P[v0] = 0.0f;
@@ -378,15 +386,15 @@ __device__ __forceinline__ void diag_factor(f32x4& D, f32x4& X, int ne, float* b
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             buf[r * 4 + v] = P[v];
-            buf[64 + r * 4 + v] = X[v];
+            if (want_x) buf[64 + r * 4 + v] = X[v];
           }
         }
         __builtin_amdgcn_wave_barrier();
         const float u = (r >= 4 * p + 4) ? buf[r * 4 + g] : 0.0f;   // L[r][4p+g]
-        const float xw = buf[64 + r * 4 + g];                        // X[r][4p+g]
+        const float xw = want_x ? buf[64 + r * 4 + g] : 0.0f;        // X[r][4p+g]
         __builtin_amdgcn_wave_barrier();
         D = mfma4(u, u, D);
-        X = mfma4(-u, xw, X);
+        if (want_x) X = mfma4(-u, xw, X);
       }
     }
   }
@@ -418,7 +426,7 @@ __device__ __forceinline__ double take_pivot_hi(double piv, double& minpiv, doub
 // row; the in-panel elimination then runs lane-locally (redundantly in the
 // four groups) and each group takes its own column back.
 __device__ __forceinline__ void diag_factor(f64x4& D, f64x4& X, int ne, double* buf, double& minpiv,
-                                            double& maxpiv, bool& bad) {
+                                            double& maxpiv, bool& bad, bool = true) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -544,7 +552,7 @@ __device__ __forceinline__ void factor_system(int n, int nb, const WaveScratch<T
     const int ne = (j == NB - 1) ? 16 - nb : 16;
     V X;
     V D = L[tix(j, j)];
-    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad);
+    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad, j < NB - 1);
     L[tix(j, j)] = D;
     if (j < NB - 1) {
       // Inv = transpose(X) through LDS, negated

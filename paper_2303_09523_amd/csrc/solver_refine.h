@@ -123,9 +123,10 @@ __device__ __forceinline__ f32x4 neg_transpose(const f32x4& x, float* buf) {
 }
 
 // Left-looking factorisation (FP32 diagonal / off-diagonal solves, UPD trailing
-// updates) keeping every L tile and every diagonal L^{-T} tile (Xs). Leaves
-// the last diagonal tile (with G in its border corner) in buf.
-template <int NB, int UPD>
+// updates) keeping every L tile and every diagonal L^{-T} tile (Xs; the last
+// one only with LAST_X, for the back-substitution). Leaves the last diagonal
+// tile (with G in its border corner) in buf.
+template <int NB, int UPD, bool LAST_X>
 __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<float>& ws,
                                             const Smem<float>& sm, int ncand, float* buf,
                                             float& minpiv, float& maxpiv, bool& bad,
@@ -166,7 +167,7 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     const int ne = (j == NB - 1) ? 16 - nb : 16;
     f32x4 X;
     f32x4 D = S[j];
-    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad);
+    diag_factor(D, X, ne, buf, minpiv, maxpiv, bad, j < NB - 1 || LAST_X);
     Xs[j] = X;
     if (j < NB - 1) {
       const f32x4 NI = neg_transpose(X, buf);
@@ -402,7 +403,7 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   mn = 3.0e38f;
   mxp = 0.0f;
   bad = false;
-  factor_keep<NB, UPD>(n, nb, ws, sm, ncand, ws.buf, mn, mxp, bad, Ls, Xs);
+  factor_keep<NB, UPD, CORR>(n, nb, ws, sm, ncand, ws.buf, mn, mxp, bad, Ls, Xs);
   const int ne = 16 - nb;
   float est_r = 0.0f;
   if (lane < ntgt) {
