@@ -84,27 +84,42 @@ __global__ void reset_cursors_kernel(DevCounters* c) {
 
 // Known slice s -> plane s*f of the volume; variance 0 there. Also latches
 // non-finite inputs and records the largest |known voxel| (the floor of the
-// per-voxel error measure of the mixed path's routing).
-__global__ void place_kernel(const float* __restrict__ slices, float* __restrict__ volume,
-                             float* __restrict__ variance, long long plane, int nslices, int f,
-                             DevCounters* ctr) {
-  long long total = plane * nslices;
+// per-voxel error measure of the mixed path's routing). Grid (x, slice); one
+// flag and one maximum per block go to the counters.
+__global__ __launch_bounds__(256) void place_kernel(const float* __restrict__ slices,
+                                                    float* __restrict__ volume,
+                                                    float* __restrict__ variance, long long plane,
+                                                    int f, DevCounters* ctr) {
+  __shared__ float wmax[4];
+  __shared__ unsigned wbad[4];
+  const long long s = blockIdx.y;
+  const float* src = slices + s * plane;
+  float* dst = volume + s * f * plane;
+  float* dvar = variance ? variance + s * f * plane : nullptr;
   bool bad = false;
   float amax = 0.0f;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    long long s = i / plane, p = i - s * plane;
-    float v = slices[i];
-    bad |= !isfinite(v);
-    if (isfinite(v)) amax = fmaxf(amax, fabsf(v));
-    long long o = s * f * plane + p;
-    volume[o] = v;
-    if (variance) variance[o] = 0.0f;
+  for (long long p = blockIdx.x * 256ll + threadIdx.x; p < plane; p += (long long)gridDim.x * 256) {
+    const float v = src[p];
+    const bool fin = isfinite(v);
+    bad |= !fin;
+    amax = fin ? fmaxf(amax, fabsf(v)) : amax;
+    dst[p] = v;
+    if (dvar) dvar[p] = 0.0f;
   }
-  if (bad) atomicOr(&ctr->nonfinite, 1u);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  if ((threadIdx.x & 63) == 0 && amax > 0.0f) atomicMax(&ctr->zmax_bits, __float_as_uint(amax));
+  const bool wb = __any(bad);
+  const int wid = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    wmax[wid] = amax;
+    wbad[wid] = wb ? 1u : 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    if (wbad[0] | wbad[1] | wbad[2] | wbad[3]) atomicOr(&ctr->nonfinite, 1u);
+    if (m > 0.0f) atomicMax(&ctr->zmax_bits, __float_as_uint(m));
+  }
 }
 
 constexpr int kSelTile = 16;
@@ -211,6 +226,11 @@ __global__ void scan_kernel(DevCounters* ctr) {
   }
 }
 
+// Each block ranks kScatterPer x 256 systems in an LDS histogram, claims its
+// range of every bucket with one global atomic per bucket, and writes the
+// systems' slots of the size-sorted permutation.
+constexpr int kScatterPer = 16;
+
 __global__ __launch_bounds__(256) void scatter_kernel(const uint8_t* __restrict__ count,
                                                       long long nsys, uint32_t* __restrict__ perm,
                                                       DevCounters* __restrict__ ctr) {
@@ -219,18 +239,28 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint8_t* __restrict_
   const int tid = threadIdx.x;
   for (int i = tid; i < kHist; i += 256) lh[i] = 0;
   __syncthreads();
-  const long long sys = blockIdx.x * 256ll + tid;
-  int n = 0;
-  unsigned int rank = 0;
-  if (sys < nsys) {
-    n = count[sys] & 0x7f;
-    rank = atomicAdd(&lh[n], 1u);
+  const long long b0 = blockIdx.x * (256ll * kScatterPer) + tid;
+  int nn[kScatterPer];
+  unsigned int rank[kScatterPer];
+#pragma unroll
+  for (int k = 0; k < kScatterPer; ++k) {
+    const long long sys = b0 + 256ll * k;
+    nn[k] = 0;
+    rank[k] = 0;
+    if (sys < nsys) {
+      nn[k] = count[sys] & 0x7f;
+      rank[k] = atomicAdd(&lh[nn[k]], 1u);
+    }
   }
   __syncthreads();
   for (int i = tid; i < kHist; i += 256)
     if (lh[i]) base[i] = ctr->offsets[i] + atomicAdd(&ctr->cursor[i], (unsigned long long)lh[i]);
   __syncthreads();
-  if (sys < nsys) perm[base[n] + rank] = (uint32_t)sys;
+#pragma unroll
+  for (int k = 0; k < kScatterPer; ++k) {
+    const long long sys = b0 + 256ll * k;
+    if (sys < nsys) perm[base[nn[k]] + rank[k]] = (uint32_t)sys;
+  }
 }
 
 }  // namespace
@@ -252,12 +282,14 @@ hipError_t launch_reset_cursors(DevCounters* c, hipStream_t s) {
 
 hipError_t launch_place(const float* slices, float* volume, float* variance, const Geometry& g,
                         DevCounters* c, hipStream_t s) {
-  long long total = g.plane * g.nslices;
-  long long blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(place_kernel, dim3((unsigned)blocks), dim3(256), 0, s, slices, volume,
-                     variance, g.plane, g.nslices, g.f, c);
+  if (g.nslices < 1 || g.plane < 1) return hipSuccess;
+  // about 2048 blocks in all, at most one thread per voxel of a plane
+  long long gx = (g.plane + 255) / 256;
+  const long long want = (2048 + g.nslices - 1) / g.nslices;
+  if (gx > want) gx = want;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(place_kernel, dim3((unsigned)gx, (unsigned)g.nslices), dim3(256), 0, s, slices,
+                     volume, variance, g.plane, g.f, c);
   return hipGetLastError();
 }
 
@@ -280,7 +312,9 @@ hipError_t launch_bucket(const uint8_t* count, const Geometry& g, uint32_t* perm
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, s, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  long long blocks = (g.nsys + 255) / 256;
+  if (g.nsys < 1) return hipSuccess;
+  const long long per = 256ll * kScatterPer;
+  const long long blocks = (g.nsys + per - 1) / per;
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, g.nsys, perm,
                      c);
   return hipGetLastError();
