@@ -8,8 +8,9 @@
 //      z_hat = z_ref + s * z_hat' and sigma^2 = sill * sigma'^2, while every
 //      low-precision operand stays O(1).
 //   2. Left-looking factorisation of [[C, B], [B^T, 0]] with FP32 diagonal
-//      tiles and off-diagonal solves and split FP16 (or BF16) MFMA trailing
-//      updates (hi*hi + hi*lo + lo*hi, FP32 accumulation).
+//      tiles and split FP16 (or BF16) MFMA trailing updates (hi*hi + hi*lo +
+//      lo*hi, FP32 accumulation); the off-diagonal solves are FP32, or split
+//      FP16 products as well in the FP16 read-out.
 //   3. Back-substitution gives x_1 = C^{-1} 1, x_z = C^{-1} z, x_t = C^{-1} c0_t,
 //      hence the weights w_t = x_t - mu_t x_1 (mu_t = (1'x_t - 1) / 1'x_1) and
 //      the adjoint vector nu_w = x_z - (1'x_z / 1'x_1) x_1 with

@@ -9,10 +9,10 @@
 // Trailing-update precisions (UPD):
 //   0  FP32 MFMA (16x16x4)
 //   1  split FP16: each L tile is kept as hi + lo halves and a product is
-//      hi*hi + hi*lo + lo*hi on 16x16x32 MFMAs with FP32 accumulation
+//      hi*hi + hi*lo + lo*hi on 16x16x16 MFMAs with FP32 accumulation
 //   2  split BF16: the same with bfloat16 halves
-// The diagonal tiles, the off-diagonal solves and the back-substitution are
-// FP32 in every case.
+// The diagonal tiles and the back-substitution are FP32 in every case, the
+// off-diagonal solves too except in the FP16 read-out (split products there).
 #pragma once
 
 #include "solver_core.h"
@@ -171,10 +171,29 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     Xs[j] = X;
     if (j < NB - 1) {
       const f32x4 NI = neg_transpose(X, buf);
+      // FP16 read-out: the off-diagonal solves as split products too (three
+      // 16-cycle MFMAs instead of four 32-cycle FP32 ones). Kept in FP32 for
+      // BF16 halves (too few bits for the explicit inverse) and for the
+      // corrected form, whose result is second order in the factor's error.
+      if constexpr (UPD != 1 || LAST_X) {
 #pragma unroll
-      for (int i = j + 1; i < NB; ++i) {
-        const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-        Ls[i][j / 2].put(j & 1, acc_qpt(z, S[i], NI));
+        for (int i = j + 1; i < NB; ++i) {
+          const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+          Ls[i][j / 2].put(j & 1, acc_qpt(z, S[i], NI));
+        }
+      } else {
+        PairStore<UPD> ns;
+        ns.put(0, NI);
+#pragma unroll
+        for (int i = j + 1; i < NB; ++i) {
+          PairStore<UPD> ss;
+          ss.put(0, S[i]);
+          f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+          z = mfma_k16(ns.lo[0], ss.hi[0], z);
+          z = mfma_k16(ns.hi[0], ss.lo[0], z);
+          z = mfma_k16(ns.hi[0], ss.hi[0], z);
+          Ls[i][j / 2].put(j & 1, z);
+        }
       }
     } else {
 #pragma unroll

@@ -214,8 +214,10 @@ def test_mixed_factor_readout_only(case, oracle_cache):
 
 def test_mixed_refine_threshold():
     """refine_tol selects the systems that take the FP64 correction: 0 takes
-    all, a threshold no estimate reaches takes none (and then equals the
-    read-out-only launch bit for bit)."""
+    all, a threshold no estimate reaches takes none, and then every system is
+    the Schur read-out. The corrected form factors with FP32 off-diagonal
+    solves and the read-out-only launch with split FP16 ones, so the two agree
+    within the read-out's error bar rather than bit for bit."""
     case = CASES[2]
     name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
     s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
@@ -227,8 +229,9 @@ def test_mixed_refine_threshold():
     vb, wb, fb, sb = run_gpu(s, e, f, r, vario, precision="mixed_fp16", flags=True, refine_tol=1.0)
     vc, wc, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", refine_max=0)
     assert sb["n_refined"] == 0
-    np.testing.assert_array_equal(vb, vc)
-    np.testing.assert_array_equal(wb, wc)
+    assert ((fb & 2) != 0).sum() == 0
+    assert rel_err_est(vb, vc.astype(np.float64), np.abs(s).max()).max() <= 1e-4
+    assert rel_err_var(wb, wc.astype(np.float64), sill).max() <= 1e-5
 
 
 def test_fp32_condition_routing():
