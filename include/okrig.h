@@ -64,6 +64,7 @@ typedef int32_t okr_status;
 #define OKR_E_OOM             5  /* device or pinned allocation failed */
 #define OKR_E_UNSUPPORTED     6  /* valid request the library does not serve */
 #define OKR_E_NOT_CONVERGED   7  /* strict mode: a system failed every precision */
+#define OKR_E_CAPACITY        8  /* caller's output buffer too small (size reported) */
 
 typedef enum { OKR_SPHERICAL = 0, OKR_EXPONENTIAL = 1, OKR_GAUSSIAN = 2 } okr_model;
 
@@ -158,6 +159,7 @@ typedef struct {
 #define OKR_PHASE_PLAIN 6
 #define OKR_PHASE_LOSO 7
 #define OKR_PHASE_PATTERN 8
+#define OKR_PHASE_MESH 9
 #define OKR_NUM_PHASES 10
 
 /* Create a plan for one problem shape. `hip_stream` is a hipStream_t (NULL =
@@ -221,6 +223,29 @@ okr_status okr_krige_points(okr_plan* plan, const okr_variogram* vario, int64_t 
                             const int32_t* d_count, const int64_t* d_offset, const float* d_xyz,
                             const float* d_val, const float* d_target_xyz, float* d_est,
                             float* d_var, float* d_weights);
+
+/* Marching cubes (Appendix C) on a float32 volume of the plan's output shape
+ * [nz][ny][nx], nz = (nslices-1)*upsample+1 -- e.g. the volume okr_execute
+ * wrote: a surface through the unit cubes between neighbouring voxels where
+ * the values cross iso. A corner is inside when its value >= iso (NaN is
+ * outside); crossing points are interpolated on the cube edge from its lower
+ * corner, t = (iso - A) / (B - A) in float32; on a face whose diagonal
+ * corners agree the crossings are paired around the inside corners, so
+ * neighbouring cubes join without holes; each polygon is oriented with its
+ * normal from inside to outside and split into a fan from its lowest edge id
+ * (corner c = x + 2y + 4z, edge 4a + u + 2w along axis a at (u, w) on the
+ * other axes). Triangles come in order of the cube index
+ * (z*(ny-1) + y)*(nx-1) + x:
+ *   d_tris   float32 [max_tris][3][3] vertex coordinates (x, y, z), voxel units
+ *   d_cube   int64 [max_tris] each triangle's cube index (nullable)
+ * *n_tris (host) receives the total number of triangles. With max_tris = 0
+ * (d_tris may then be NULL) only the count is taken; otherwise the first
+ * min(total, max_tris) triangles are written and OKR_E_CAPACITY is returned if
+ * total > max_tris. Non-finite values give NaN coordinates on their edges.
+ * Synchronises the plan's stream; the workspace (4 KB table and 12 bytes per
+ * 1024 cubes of a row) is allocated by the first call. */
+okr_status okr_marching_cubes(okr_plan* plan, const float* d_volume, float iso, float* d_tris,
+                              int64_t* d_cube, int64_t max_tris, int64_t* n_tris);
 
 /* Counters of the last execute / loso call; synchronises the plan's stream and
  * returns any latched device-side error (e.g. OKR_E_NONFINITE). */

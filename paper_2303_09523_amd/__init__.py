@@ -155,6 +155,30 @@ class Plan:
                                            _ptr(var), _ptr(w)), self._h)
         return est, var, w
 
+    def marching_cubes(self, volume, iso, max_tris=None, want_ids=True):
+        """Triangles of the iso-surface of a volume of the plan's output shape
+        (okr_marching_cubes): float32 [T][3][3] vertex coordinates (x, y, z)
+        and, with want_ids, int64 [T] cube indices, both CUDA tensors. With
+        max_tris None the triangles are counted first and the buffers sized
+        to fit."""
+        torch = _torch()
+        self._check_in(volume, torch.float32, self.out_shape(), "volume")
+        lib = load()
+        n = C.c_int64(0)
+        if max_tris is None:
+            _lib.check(lib.okr_marching_cubes(self._h, _ptr(volume), C.c_float(iso), None, None,
+                                              0, C.byref(n)), self._h)
+            max_tris = n.value
+        tris = torch.empty((max(int(max_tris), 0), 3, 3), dtype=torch.float32,
+                           device=volume.device)
+        ids = torch.empty((tris.shape[0],), dtype=torch.int64, device=volume.device) \
+            if want_ids else None
+        if tris.shape[0] > 0:
+            _lib.check(lib.okr_marching_cubes(self._h, _ptr(volume), C.c_float(iso), _ptr(tris),
+                                              _ptr(ids), tris.shape[0], C.byref(n)), self._h)
+        T = min(n.value, tris.shape[0])
+        return tris[:T], (ids[:T] if ids is not None else None)
+
     def select(self, edge=None):
         """Kept-candidate bitmasks [(n-1)*ny*nx][2] (int64 view of uint64) and counts."""
         torch = _torch()

@@ -14,9 +14,10 @@ LIB_PATH = os.path.join(HERE, "libokrig.so")
 OKR_OK = 0
 STATUS_NAMES = {0: "OKR_OK", 1: "OKR_E_INVALID_ARG", 2: "OKR_E_SHAPE", 3: "OKR_E_NONFINITE",
                 4: "OKR_E_DEVICE", 5: "OKR_E_OOM", 6: "OKR_E_UNSUPPORTED",
-                7: "OKR_E_NOT_CONVERGED"}
+                7: "OKR_E_NOT_CONVERGED", 8: "OKR_E_CAPACITY"}
 MODELS = {"spherical": 0, "exponential": 1, "gaussian": 2}
-PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso", "pattern"]
+PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso", "pattern",
+          "mesh"]
 PRECISIONS = {"fp32": 0, "mixed_fp16": 1, "mixed_bf16": 2, "fp64": 3}
 ALGOS = {"batched": 0, "plain": 1, "pattern": 2}
 
@@ -24,7 +25,7 @@ EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
             "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling",
             "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning",
-            "okr_krige_points"]
+            "okr_krige_points", "okr_marching_cubes"]
 
 
 class Variogram(C.Structure):
@@ -83,6 +84,8 @@ def load():
         "okr_krige_points": (C.c_int32, [VP, P(Variogram), C.c_int64, VP, VP, VP, VP, VP, VP,
                                          VP, VP]),
         "okr_plan_autotune": (C.c_int32, [VP, P(Variogram), VP, VP, VP, VP]),
+        "okr_marching_cubes": (C.c_int32, [VP, VP, C.c_float, VP, VP, C.c_int64,
+                                           P(C.c_int64)]),
         "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double)]),
     }
     for name, (res, args) in sig.items():

@@ -41,6 +41,9 @@ struct okr_plan {
   double* loso_resid = nullptr;   // per held-out voxel residual (z_hat - z)
   double* loso_gpart = nullptr;   // per held-out voxel gradient contribution [3]
   double* loso_partial = nullptr; // reduction partials
+  okr::McTable* mc_tab = nullptr;     // marching cubes: case table,
+  uint32_t* mc_cnt = nullptr;         // triangles per workgroup,
+  unsigned long long* mc_off = nullptr; // their offsets and the total (first call)
   bool loso_ready = false;
   okr_variogram loso_vario{};
   const float* loso_slices = nullptr;
@@ -234,6 +237,9 @@ void free_plan(okr_plan* p) {
   hipFree(p->loso_resid);
   hipFree(p->loso_gpart);
   hipFree(p->loso_partial);
+  hipFree(p->mc_tab);
+  hipFree(p->mc_cnt);
+  hipFree(p->mc_off);
   delete p;
 }
 
@@ -346,6 +352,7 @@ const char* okr_status_string(okr_status s) {
     case OKR_E_OOM: return "out of memory";
     case OKR_E_UNSUPPORTED: return "unsupported";
     case OKR_E_NOT_CONVERGED: return "not converged";
+    case OKR_E_CAPACITY: return "output buffer too small";
     default: return "unknown status";
   }
 }
@@ -667,6 +674,58 @@ okr_status okr_krige_points(okr_plan* p, const okr_variogram* vario, int64_t nsy
                                 p->stream));
   p->last_nsys = nsys;
   p->last_kriged = nsys;
+  return OKR_OK;
+}
+
+okr_status okr_marching_cubes(okr_plan* p, const float* d_volume, float iso, float* d_tris,
+                              int64_t* d_cube, int64_t max_tris, int64_t* n_tris) {
+  if (!p) return OKR_E_INVALID_ARG;
+  if (!d_volume || !n_tris) return fail(p, OKR_E_INVALID_ARG, "volume and n_tris are required");
+  if (max_tris < 0) return fail(p, OKR_E_INVALID_ARG, "max_tris must be >= 0");
+  if (max_tris > 0 && !d_tris) return fail(p, OKR_E_INVALID_ARG, "tris is required when max_tris > 0");
+  *n_tris = 0;
+  const okr::Geometry& g = p->geo;
+  const long long nz = (long long)(g.nslices - 1) * g.f + 1, ny = g.ny, nx = g.nx;
+  if (g.nslices < 1 || nz < 2 || ny < 2 || nx < 2) return OKR_OK;
+  const long long rows = (nz - 1) * (ny - 1);
+  const long long nseg = (nx - 1 + okr::kMcRun - 1) / okr::kMcRun;
+  const long long nblk = rows * nseg;
+  if (nblk > 0x7fffffffLL) return fail(p, OKR_E_SHAPE, "volume too large for marching cubes");
+  if (!p->mc_tab) {
+    const okr::McTable& t = okr::mc_table();
+    if (hipMalloc(&p->mc_tab, sizeof(okr::McTable)) != hipSuccess ||
+        hipMalloc(&p->mc_cnt, sizeof(uint32_t) * nblk) != hipSuccess ||
+        hipMalloc(&p->mc_off, sizeof(unsigned long long) * (nblk + 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      hipFree(p->mc_tab);
+      hipFree(p->mc_cnt);
+      hipFree(p->mc_off);
+      p->mc_tab = nullptr;
+      p->mc_cnt = nullptr;
+      p->mc_off = nullptr;
+      return fail(p, OKR_E_OOM, "marching cubes workspace");
+    }
+    OKR_HIP(p, hipMemcpy(p->mc_tab, &t, sizeof(t), hipMemcpyHostToDevice));
+  }
+  unsigned long long total = 0;
+  {
+    PhaseTimer t(p, OKR_PHASE_MESH);
+    OKR_HIP(p, okr::launch_mc_count(d_volume, (int)nx, (int)ny, nblk, (int)nseg, iso, p->mc_tab,
+                                    p->mc_cnt, p->stream));
+    OKR_HIP(p, okr::launch_mc_scan(p->mc_cnt, nblk, p->mc_off, p->stream));
+    if (max_tris > 0)
+      OKR_HIP(p, okr::launch_mc_emit(d_volume, (int)nx, (int)ny, nblk, (int)nseg, iso, p->mc_tab,
+                                     p->mc_off, d_tris, (long long*)d_cube, (long long)max_tris,
+                                     p->stream));
+  }
+  OKR_HIP(p, hipMemcpyAsync(&total, p->mc_off + nblk, sizeof(total), hipMemcpyDeviceToHost,
+                            p->stream));
+  OKR_HIP(p, hipStreamSynchronize(p->stream));
+  *n_tris = (int64_t)total;
+  if (max_tris > 0 && (long long)total > max_tris)
+    return fail(p, OKR_E_CAPACITY,
+                "marching cubes: " + std::to_string(total) + " triangles, buffer holds " +
+                    std::to_string(max_tris));
   return OKR_OK;
 }
 

@@ -136,4 +136,21 @@ hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, 
 hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume, float* variance,
                         const Geometry& g, const SelectRule& rule, const Vario& v, hipStream_t s);
 
+// ---- marching cubes (mcubes_table.cpp, kernels_mcubes.hip) ----
+constexpr int kMcMaxTri = 5;     // triangles of one cube configuration, at most
+constexpr int kMcRun = 1024;     // cubes of one (z, y) row per workgroup
+struct McTable {
+  uint8_t ntri[256];                  // triangles of configuration cfg
+  uint8_t tri[256][3 * kMcMaxTri];    // their cube edges, three per triangle
+};
+const McTable& mc_table();            // built once on the host
+// Workgroups: ((nz-1)(ny-1) rows) x nseg runs, nseg = ceil((nx-1) / kMcRun).
+hipError_t launch_mc_count(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
+                           const McTable* table, uint32_t* block_tris, hipStream_t s);
+hipError_t launch_mc_scan(const uint32_t* block_tris, long long nblk, unsigned long long* off,
+                          hipStream_t s);
+hipError_t launch_mc_emit(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
+                          const McTable* table, const unsigned long long* off, float* tris,
+                          long long* cube_id, long long max_tris, hipStream_t s);
+
 }  // namespace okr
