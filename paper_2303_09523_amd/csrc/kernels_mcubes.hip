@@ -2,211 +2,360 @@
 // table (mcubes_table.cpp) gives each corner configuration's triangles as
 // cube-edge triples; crossing points are interpolated on their edges.
 //
-// HBM-bound. Three launches: count (triangles per workgroup), scan (one
-// workgroup turns the counts into output offsets) and emit (recounts, ranks
-// the cubes of the workgroup in index order and writes the triangles). A
-// workgroup takes a run of up to kMcRun cubes of one (z, y) row, four per
-// thread, so its eight corner loads per cube are four coalesced row reads,
-// and the output keeps the cube order without storing per-cube counts.
+// HBM-bound. Four launches: count, two scan levels, emit. A wave takes a
+// strip of 64 cubes of one z-slab over kMcRows rows and slides down y,
+// keeping the previous row's corner values in registers, so each cube loads
+// its four new corners (two coalesced row reads per z-level). Counts are kept
+// per (row, strip): count and emit need no workgroup barrier, and the scans
+// turn them into output offsets that keep the cube order.
 #include "okrig_internal.h"
 
 namespace okr {
 namespace {
 
-constexpr int kMcThreads = 256;
-constexpr int kMcPer = kMcRun / kMcThreads;
-
-struct McRow {
-  const float* r00;   // (z, y)
-  const float* r01;   // (z, y + 1)
-  const float* r10;   // (z + 1, y)
-  const float* r11;   // (z + 1, y + 1)
-  int z, y, x0;
+// One wave's strip of cubes: z-slab z, rows [y0, y1), columns x = x0 + lane.
+struct McStrip {
+  const float* p0;    // plane z
+  const float* p1;    // plane z + 1
+  int x, y0, y1, z;
+  long long strip, nstrip;
 };
 
-__device__ __forceinline__ McRow mc_row(const float* vol, int nx, int ny, int nseg) {
-  const long long b = blockIdx.x;
-  const long long row = b / nseg;
-  McRow m;
-  m.x0 = (int)(b - row * nseg) * kMcRun;
-  m.z = (int)(row / (ny - 1));
-  m.y = (int)(row - (long long)m.z * (ny - 1));
+__device__ __forceinline__ McStrip mc_strip(const float* vol, int nx, int ny, int nstrip,
+                                            int nych) {
+  const long long wave = blockIdx.x * 4ll + (threadIdx.x >> 6);
+  McStrip m;
+  m.nstrip = nstrip;
+  m.strip = wave % nstrip;
+  const long long t = wave / nstrip;
+  const int ych = (int)(t % nych);
+  m.z = (int)(t / nych);
+  m.x = (int)m.strip * 64 + (int)(threadIdx.x & 63);
+  m.y0 = ych * kMcRows;
+  m.y1 = m.y0 + kMcRows < ny - 1 ? m.y0 + kMcRows : ny - 1;
   const long long plane = (long long)nx * ny;
-  m.r00 = vol + m.z * plane + (long long)m.y * nx;
-  m.r01 = m.r00 + nx;
-  m.r10 = m.r00 + plane;
-  m.r11 = m.r10 + nx;
+  m.p0 = vol + m.z * plane;
+  m.p1 = m.p0 + plane;
   return m;
 }
 
-// Corner values (c = x + 2y + 4z) of the cube at x and its configuration
-// (bit c set when corner c is inside: value >= iso; NaN is outside).
-__device__ __forceinline__ int mc_config(const McRow& m, int x, float iso, float (&v)[8]) {
-  v[0] = m.r00[x];
-  v[1] = m.r00[x + 1];
-  v[2] = m.r01[x];
-  v[3] = m.r01[x + 1];
-  v[4] = m.r10[x];
-  v[5] = m.r10[x + 1];
-  v[6] = m.r11[x];
-  v[7] = m.r11[x + 1];
+// Corner values of row y at column x: (x, z), (x+1, z), (x, z+1), (x+1, z+1).
+struct McPair {
+  float a, b, c, d;
+};
+
+__device__ __forceinline__ McPair mc_load(const McStrip& m, int nx, int y) {
+  const long long o = (long long)y * nx + m.x;
+  return {m.p0[o], m.p0[o + 1], m.p1[o], m.p1[o + 1]};
+}
+
+// Corners c = x + 2y + 4z of the cube between rows y (lo) and y + 1 (hi);
+// bit c of the configuration set when corner c is inside (value >= iso,
+// NaN outside).
+__device__ __forceinline__ int mc_cfg(const McPair& lo, const McPair& hi, float iso,
+                                      float (&v)[8]) {
+  v[0] = lo.a; v[1] = lo.b; v[2] = hi.a; v[3] = hi.b;
+  v[4] = lo.c; v[5] = lo.d; v[6] = hi.c; v[7] = hi.d;
   int cfg = 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) cfg |= (v[c] >= iso) ? (1 << c) : 0;
   return cfg;
 }
 
-__device__ __forceinline__ unsigned block_sum(unsigned x, unsigned* red) {
+// Rows y + 1 .. y + kMcGroup (those before m.y1) of the strip.
+__device__ __forceinline__ void mc_load_group(const McStrip& m, int nx, int y, bool valid,
+                                              McPair (&g)[kMcGroup]) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  const int wid = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[wid] = x;
-  __syncthreads();
-  const unsigned s = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  return s;
+  for (int k = 0; k < kMcGroup; ++k)
+    g[k] = (valid && y + k < m.y1) ? mc_load(m, nx, y + k + 1) : McPair{0, 0, 0, 0};
 }
 
-__global__ __launch_bounds__(kMcThreads) void mc_count_kernel(const float* __restrict__ vol, int nx,
-                                                              int ny, int nseg, float iso,
-                                                              const McTable* __restrict__ table,
-                                                              uint32_t* __restrict__ block_tris) {
+// Triangle counts are 0..5: three bits. The wave's total and each lane's
+// exclusive prefix come from one ballot per bit (popcounts on the scalar unit,
+// lane-masked counts with mbcnt), without a shuffle through LDS.
+struct McBits {
+  uint64_t b0, b1, b2;
+};
+
+__device__ __forceinline__ McBits mc_bits(unsigned n) {
+  return {__ballot(n & 1u), __ballot(n & 2u), __ballot(n & 4u)};
+}
+
+__device__ __forceinline__ unsigned mc_total(const McBits& b) {
+  return (unsigned)(__popcll(b.b0) + 2 * __popcll(b.b1) + 4 * __popcll(b.b2));
+}
+
+__device__ __forceinline__ unsigned mbcnt64(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ unsigned mc_prefix(const McBits& b) {
+  return mbcnt64(b.b0) + 2u * mbcnt64(b.b1) + 4u * mbcnt64(b.b2);
+}
+
+// count of (row, strip) at index row * nstrip + strip, row = z * (ny-1) + y
+__global__ __launch_bounds__(256) void mc_count_kernel(const float* __restrict__ vol, int nx,
+                                                       int ny, int nstrip, int nych,
+                                                       long long nwaves, float iso,
+                                                       const McTable* __restrict__ table,
+                                                       uint32_t* __restrict__ cnt) {
   __shared__ uint8_t ntri[256];
-  __shared__ unsigned red[4];
   ntri[threadIdx.x] = table->ntri[threadIdx.x];
   __syncthreads();
-  const McRow m = mc_row(vol, nx, ny, nseg);
-  unsigned cnt = 0;
+  if (blockIdx.x * 4ll + (threadIdx.x >> 6) >= nwaves) return;
+  const McStrip m = mc_strip(vol, nx, ny, nstrip, nych);
+  const bool valid = m.x < nx - 1;
+  McPair lo = valid ? mc_load(m, nx, m.y0) : McPair{0, 0, 0, 0};
+  // rows in groups of kMcGroup; the next group's loads are issued before the
+  // current group is classified, for memory-level parallelism
+  McPair cur[kMcGroup], nxt[kMcGroup];
+  mc_load_group(m, nx, m.y0, valid, cur);
+  for (int y = m.y0; y < m.y1; y += kMcGroup) {
+    mc_load_group(m, nx, y + kMcGroup, valid, nxt);
 #pragma unroll
-  for (int k = 0; k < kMcPer; ++k) {
-    const int x = m.x0 + k * kMcThreads + (int)threadIdx.x;
-    if (x < nx - 1) {
-      float v[8];
-      cnt += ntri[mc_config(m, x, iso, v)];
+    for (int k = 0; k < kMcGroup; ++k) {
+      if (y + k < m.y1) {
+        float v[8];
+        const unsigned n = valid ? ntri[mc_cfg(lo, cur[k], iso, v)] : 0u;
+        const unsigned tot = mc_total(mc_bits(n));
+        if ((threadIdx.x & 63) == 0)
+          cnt[((long long)m.z * (ny - 1) + y + k) * m.nstrip + m.strip] = tot;
+        lo = cur[k];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < kMcGroup; ++k) cur[k] = nxt[k];
   }
-  const unsigned s = block_sum(cnt, red);
-  if (threadIdx.x == 0) block_tris[blockIdx.x] = s;
 }
 
-// Exclusive prefix sums of the per-workgroup counts (one workgroup of 1024
-// threads, each summing a contiguous chunk); off[nblk] is the total.
-__global__ __launch_bounds__(1024) void mc_scan_kernel(const uint32_t* __restrict__ block_tris,
-                                                       long long nblk,
-                                                       unsigned long long* __restrict__ off) {
-  __shared__ unsigned long long part[1024];
-  const long long chunk = (nblk + 1023) / 1024;
-  const long long b0 = threadIdx.x * chunk;
-  const long long b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
-  unsigned long long s = 0;
-  for (long long b = b0; b < b1; ++b) s += block_tris[b];
-  part[threadIdx.x] = s;
+// Level 1: each workgroup turns 1024 counts into offsets within the tile (in
+// place) and records the tile's total.
+__global__ __launch_bounds__(1024) void mc_scan_tiles_kernel(uint32_t* __restrict__ cnt,
+                                                             long long ncnt,
+                                                             unsigned long long* __restrict__ tile_sum) {
+  __shared__ unsigned wtot[16];
+  const long long i = blockIdx.x * 1024ll + threadIdx.x;
+  const unsigned c = i < ncnt ? cnt[i] : 0u;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned inc = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wtot[wid] = inc;
   __syncthreads();
-  // inclusive scan of the 1024 chunk sums (Hillis-Steele in LDS)
-  for (int d = 1; d < 1024; d <<= 1) {
-    const unsigned long long add = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0ull;
-    __syncthreads();
-    part[threadIdx.x] += add;
-    __syncthreads();
+  unsigned before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    before += w < wid ? wtot[w] : 0u;
+    total += wtot[w];
   }
-  unsigned long long run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
-  for (long long b = b0; b < b1; ++b) {
-    off[b] = run;
-    run += block_tris[b];
-  }
-  if (threadIdx.x == 1023) off[nblk] = part[1023];
+  if (i < ncnt) cnt[i] = before + inc - c;
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kMcThreads) void mc_emit_kernel(
-    const float* __restrict__ vol, int nx, int ny, int nseg, float iso,
-    const McTable* __restrict__ table, const unsigned long long* __restrict__ off,
-    float* __restrict__ tris, long long* __restrict__ cube_id, long long max_tris) {
+// Level 2 (one workgroup): exclusive offsets of the tiles, in place;
+// tile_sum[ntile] receives the total.
+__global__ __launch_bounds__(1024) void mc_scan_top_kernel(unsigned long long* __restrict__ tile_sum,
+                                                           long long ntile) {
+  __shared__ unsigned long long wtot[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  unsigned long long carry = 0;
+  for (long long base = 0; base < ntile; base += 1024) {
+    const long long i = base + threadIdx.x;
+    const unsigned long long c = i < ntile ? tile_sum[i] : 0ull;
+    unsigned long long inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    unsigned long long before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      before += w < wid ? wtot[w] : 0ull;
+      total += wtot[w];
+    }
+    __syncthreads();
+    if (i < ntile) tile_sum[i] = carry + before + inc - c;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tile_sum[ntile] = carry;
+}
+
+// Per-wave queue of the emit pass: the cubes that have triangles
+// (configuration, column and row, first output slot) and one task per
+// triangle (cube slot << 3 | triangle); the corner values are read again
+// (from cache) when the triangles are computed. Rows are appended until 64 or more
+// triangles wait; the wave then computes them one per lane, so consecutive
+// lanes write consecutive triangles. Capacity: fewer than 64 waiting plus one
+// row's at most 5 x 64.
+constexpr int kMcQCubes = 128;
+constexpr int kMcQTris = 64 + 5 * 64;
+struct McQueue {
+  unsigned long long first[kMcQCubes];
+  int x[kMcQCubes], y[kMcQCubes];
+  uint8_t cfg[kMcQCubes];
+  unsigned task[kMcQTris];
+};
+
+__device__ __forceinline__ void mc_flush(McQueue& q, int ntask, const McTable& tab,
+                                         const McStrip& m, int nx, int ny, float iso,
+                                         float* __restrict__ tris,
+                                         long long* __restrict__ cube_id, long long max_tris) {
+  const int z = m.z;
+  const int lane = threadIdx.x & 63;
+  for (int t = lane; t < ntask; t += 64) {
+    const unsigned task = q.task[t];
+    const int slot = (int)(task >> 3), j = (int)(task & 7);
+    const long long o = (long long)(q.first[slot] + j);
+    if (o >= max_tris) continue;
+    const int cfg = q.cfg[slot];
+    const int x = q.x[slot], y = q.y[slot];
+    const long long r0 = (long long)y * nx + x, r1 = r0 + nx;
+    const float v[8] = {m.p0[r0], m.p0[r0 + 1], m.p0[r1], m.p0[r1 + 1],
+                        m.p1[r0], m.p1[r0 + 1], m.p1[r1], m.p1[r1 + 1]};
+    float out[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int ed = tab.tri[cfg][3 * j + k];
+      const int axis = ed >> 2;
+      // lower corner of the edge: bit `axis` clear, the edge's (u, w) on the
+      // other two axes
+      const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
+      const int lc = ((ed & 1) << b0) | (((ed >> 1) & 1) << b1);
+      const int hc = lc | (1 << axis);
+      float A = v[0], B = v[0];
+#pragma unroll
+      for (int c = 1; c < 8; ++c) {
+        A = lc == c ? v[c] : A;
+        B = hc == c ? v[c] : B;
+      }
+      const float tt = __fdiv_rn(iso - A, B - A);
+      float p[3] = {(float)(x + (lc & 1)), (float)(y + ((lc >> 1) & 1)),
+                    (float)(z + ((lc >> 2) & 1))};
+      p[axis] = p[axis] + tt;
+      out[3 * k + 0] = p[0];
+      out[3 * k + 1] = p[1];
+      out[3 * k + 2] = p[2];
+    }
+    float* dst = tris + 9 * o;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dst[k] = out[k];
+    if (cube_id) cube_id[o] = ((long long)z * (ny - 1) + y) * (nx - 1) + x;
+  }
+}
+
+__global__ __launch_bounds__(256) void mc_emit_kernel(
+    const float* __restrict__ vol, int nx, int ny, int nstrip, int nych, long long nwaves,
+    float iso, const McTable* __restrict__ table, const uint32_t* __restrict__ off_local,
+    const unsigned long long* __restrict__ tile_off, float* __restrict__ tris,
+    long long* __restrict__ cube_id, long long max_tris) {
   __shared__ McTable tab;
-  __shared__ unsigned wsum[4];
+  __shared__ McQueue queues[4];
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(table);
     uint32_t* dst = reinterpret_cast<uint32_t*>(&tab);
-    for (int i = threadIdx.x; i < (int)(sizeof(McTable) / 4); i += kMcThreads) dst[i] = src[i];
+    for (int i = threadIdx.x; i < (int)(sizeof(McTable) / 4); i += 256) dst[i] = src[i];
   }
   __syncthreads();
-  const McRow m = mc_row(vol, nx, ny, nseg);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  unsigned long long base = off[blockIdx.x];
-  const long long rowbase = ((long long)m.z * (ny - 1) + m.y) * (nx - 1);
-#pragma unroll 1
-  for (int k = 0; k < kMcPer; ++k) {
-    const int x = m.x0 + k * kMcThreads + (int)threadIdx.x;
-    float v[8];
-    int cfg = 0, n = 0;
-    if (x < nx - 1) {
-      cfg = mc_config(m, x, iso, v);
-      n = tab.ntri[cfg];
-    }
-    // rank among the workgroup's cubes of this pass, in x order
-    unsigned inc = (unsigned)n;
+  if (blockIdx.x * 4ll + (threadIdx.x >> 6) >= nwaves) return;
+  McQueue& q = queues[threadIdx.x >> 6];
+  const McStrip m = mc_strip(vol, nx, ny, nstrip, nych);
+  const bool valid = m.x < nx - 1;
+  const int lane = threadIdx.x & 63;
+  // output offsets of the strip's rows, one row per lane (kMcRows <= 64)
+  unsigned long long row_off = 0;
+  if (m.y0 + lane < m.y1) {
+    const long long e = ((long long)m.z * (ny - 1) + m.y0 + lane) * m.nstrip + m.strip;
+    row_off = tile_off[e >> 10] + off_local[e];
+  }
+  int ncube = 0, ntask = 0;
+  McPair lo = valid ? mc_load(m, nx, m.y0) : McPair{0, 0, 0, 0};
+  McPair hi[kMcGroup], nxt[kMcGroup];
+  mc_load_group(m, nx, m.y0, valid, hi);
+  for (int y = m.y0; y < m.y1; y += kMcGroup) {
+    mc_load_group(m, nx, y + kMcGroup, valid, nxt);
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned t = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += t;
-    }
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    unsigned before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      before += w < wid ? wsum[w] : 0u;
-      total += wsum[w];
-    }
-    __syncthreads();
-    const unsigned long long first = base + before + inc - (unsigned)n;
-    for (int j = 0; j < n; ++j) {
-      const long long o = (long long)(first + j);
-      if (o >= max_tris) break;
-      float* t = tris + 9 * o;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int e = tab.tri[cfg][3 * j + q];
-        const int axis = e >> 2;
-        // lower corner of the edge: bit `axis` clear, the edge's (u, w) on
-        // the other two axes
-        const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
-        const int lo = ((e & 1) << b0) | (((e >> 1) & 1) << b1);
-        const int hi = lo | (1 << axis);
-        const float A = v[lo], B = v[hi];
-        const float tt = __fdiv_rn(iso - A, B - A);
-        float p[3] = {(float)(x + (lo & 1)), (float)(m.y + ((lo >> 1) & 1)),
-                      (float)(m.z + ((lo >> 2) & 1))};
-        p[axis] = p[axis] + tt;
-        t[3 * q + 0] = p[0];
-        t[3 * q + 1] = p[1];
-        t[3 * q + 2] = p[2];
+    for (int k = 0; k < kMcGroup; ++k) {
+      if (y + k >= m.y1) break;
+      float v[8];
+      const int cfg = valid ? mc_cfg(lo, hi[k], iso, v) : 0;
+      const int n = valid ? tab.ntri[cfg] : 0;
+      const McBits bits = mc_bits((unsigned)n);
+      const unsigned pre = mc_prefix(bits), total = mc_total(bits);
+      const unsigned r_lo =
+          __builtin_amdgcn_readlane((unsigned)(row_off & 0xffffffffu), y + k - m.y0);
+      const unsigned r_hi = __builtin_amdgcn_readlane((unsigned)(row_off >> 32), y + k - m.y0);
+      const unsigned long long rbase = ((unsigned long long)r_hi << 32) | r_lo;
+      const uint64_t has = __ballot(n > 0);
+      if (n > 0) {
+        const int slot = ncube + (int)mbcnt64(has);
+        q.first[slot] = rbase + pre;
+        q.x[slot] = m.x;
+        q.y[slot] = y + k;
+        q.cfg[slot] = (uint8_t)cfg;
+        for (int j = 0; j < n; ++j) q.task[ntask + pre + j] = ((unsigned)slot << 3) | (unsigned)j;
       }
-      if (cube_id) cube_id[o] = rowbase + x;
+      ncube += __popcll(has);
+      ntask += (int)total;
+      lo = hi[k];
+      if (ntask >= 64) {
+        __builtin_amdgcn_wave_barrier();
+        mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
+        __builtin_amdgcn_wave_barrier();
+        ncube = 0;
+        ntask = 0;
+      }
     }
-    base += total;
+#pragma unroll
+    for (int k = 0; k < kMcGroup; ++k) hi[k] = nxt[k];
+  }
+  if (ntask > 0) {
+    __builtin_amdgcn_wave_barrier();
+    mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
   }
 }
 
 }  // namespace
 
-hipError_t launch_mc_count(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
-                           const McTable* table, uint32_t* block_tris, hipStream_t s) {
-  hipLaunchKernelGGL(mc_count_kernel, dim3((unsigned)nblk), dim3(kMcThreads), 0, s, vol, nx, ny,
-                     nseg, iso, table, block_tris);
+McGrid mc_grid(long long nz, long long ny, long long nx) {
+  McGrid g;
+  g.nstrip = (nx - 1 + 63) / 64;
+  g.nych = (ny - 1 + kMcRows - 1) / kMcRows;
+  g.nwaves = (nz - 1) * g.nych * g.nstrip;
+  g.ncnt = (nz - 1) * (ny - 1) * g.nstrip;
+  g.ntile = (g.ncnt + 1023) / 1024;
+  return g;
+}
+
+hipError_t launch_mc_count(const float* vol, int nx, int ny, const McGrid& g, float iso,
+                           const McTable* table, uint32_t* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(mc_count_kernel, dim3((unsigned)((g.nwaves + 3) / 4)), dim3(256), 0, s, vol,
+                     nx, ny, (int)g.nstrip, (int)g.nych, g.nwaves, iso, table, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_mc_scan(const uint32_t* block_tris, long long nblk, unsigned long long* off,
+hipError_t launch_mc_scan(uint32_t* cnt, const McGrid& g, unsigned long long* tile,
                           hipStream_t s) {
-  hipLaunchKernelGGL(mc_scan_kernel, dim3(1), dim3(1024), 0, s, block_tris, nblk, off);
+  hipLaunchKernelGGL(mc_scan_tiles_kernel, dim3((unsigned)g.ntile), dim3(1024), 0, s, cnt, g.ncnt,
+                     tile);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mc_scan_top_kernel, dim3(1), dim3(1024), 0, s, tile, g.ntile);
   return hipGetLastError();
 }
 
-hipError_t launch_mc_emit(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
-                          const McTable* table, const unsigned long long* off, float* tris,
-                          long long* cube_id, long long max_tris, hipStream_t s) {
-  hipLaunchKernelGGL(mc_emit_kernel, dim3((unsigned)nblk), dim3(kMcThreads), 0, s, vol, nx, ny,
-                     nseg, iso, table, off, tris, cube_id, max_tris);
+hipError_t launch_mc_emit(const float* vol, int nx, int ny, const McGrid& g, float iso,
+                          const McTable* table, const uint32_t* off_local,
+                          const unsigned long long* tile_off, float* tris, long long* cube_id,
+                          long long max_tris, hipStream_t s) {
+  hipLaunchKernelGGL(mc_emit_kernel, dim3((unsigned)((g.nwaves + 3) / 4)), dim3(256), 0, s, vol,
+                     nx, ny, (int)g.nstrip, (int)g.nych, g.nwaves, iso, table, off_local,
+                     tile_off, tris, cube_id, max_tris);
   return hipGetLastError();
 }
 

@@ -41,9 +41,9 @@ struct okr_plan {
   double* loso_resid = nullptr;   // per held-out voxel residual (z_hat - z)
   double* loso_gpart = nullptr;   // per held-out voxel gradient contribution [3]
   double* loso_partial = nullptr; // reduction partials
-  okr::McTable* mc_tab = nullptr;     // marching cubes: case table,
-  uint32_t* mc_cnt = nullptr;         // triangles per workgroup,
-  unsigned long long* mc_off = nullptr; // their offsets and the total (first call)
+  okr::McTable* mc_tab = nullptr;       // marching cubes (first call): case table,
+  uint32_t* mc_cnt = nullptr;           // triangles per (row, strip), then offsets,
+  unsigned long long* mc_tile = nullptr;  // tile offsets and the total
   bool loso_ready = false;
   okr_variogram loso_vario{};
   const float* loso_slices = nullptr;
@@ -239,7 +239,7 @@ void free_plan(okr_plan* p) {
   hipFree(p->loso_partial);
   hipFree(p->mc_tab);
   hipFree(p->mc_cnt);
-  hipFree(p->mc_off);
+  hipFree(p->mc_tile);
   delete p;
 }
 
@@ -687,22 +687,21 @@ okr_status okr_marching_cubes(okr_plan* p, const float* d_volume, float iso, flo
   const okr::Geometry& g = p->geo;
   const long long nz = (long long)(g.nslices - 1) * g.f + 1, ny = g.ny, nx = g.nx;
   if (g.nslices < 1 || nz < 2 || ny < 2 || nx < 2) return OKR_OK;
-  const long long rows = (nz - 1) * (ny - 1);
-  const long long nseg = (nx - 1 + okr::kMcRun - 1) / okr::kMcRun;
-  const long long nblk = rows * nseg;
-  if (nblk > 0x7fffffffLL) return fail(p, OKR_E_SHAPE, "volume too large for marching cubes");
+  const okr::McGrid mg = okr::mc_grid(nz, ny, nx);
+  if ((mg.nwaves + 3) / 4 > 0x7fffffffLL || mg.ntile > 0x7fffffffLL)
+    return fail(p, OKR_E_SHAPE, "volume too large for marching cubes");
   if (!p->mc_tab) {
     const okr::McTable& t = okr::mc_table();
     if (hipMalloc(&p->mc_tab, sizeof(okr::McTable)) != hipSuccess ||
-        hipMalloc(&p->mc_cnt, sizeof(uint32_t) * nblk) != hipSuccess ||
-        hipMalloc(&p->mc_off, sizeof(unsigned long long) * (nblk + 1)) != hipSuccess) {
+        hipMalloc(&p->mc_cnt, sizeof(uint32_t) * mg.ncnt) != hipSuccess ||
+        hipMalloc(&p->mc_tile, sizeof(unsigned long long) * (mg.ntile + 1)) != hipSuccess) {
       (void)hipGetLastError();
       hipFree(p->mc_tab);
       hipFree(p->mc_cnt);
-      hipFree(p->mc_off);
+      hipFree(p->mc_tile);
       p->mc_tab = nullptr;
       p->mc_cnt = nullptr;
-      p->mc_off = nullptr;
+      p->mc_tile = nullptr;
       return fail(p, OKR_E_OOM, "marching cubes workspace");
     }
     OKR_HIP(p, hipMemcpy(p->mc_tab, &t, sizeof(t), hipMemcpyHostToDevice));
@@ -710,15 +709,15 @@ okr_status okr_marching_cubes(okr_plan* p, const float* d_volume, float iso, flo
   unsigned long long total = 0;
   {
     PhaseTimer t(p, OKR_PHASE_MESH);
-    OKR_HIP(p, okr::launch_mc_count(d_volume, (int)nx, (int)ny, nblk, (int)nseg, iso, p->mc_tab,
-                                    p->mc_cnt, p->stream));
-    OKR_HIP(p, okr::launch_mc_scan(p->mc_cnt, nblk, p->mc_off, p->stream));
+    OKR_HIP(p, okr::launch_mc_count(d_volume, (int)nx, (int)ny, mg, iso, p->mc_tab, p->mc_cnt,
+                                    p->stream));
+    OKR_HIP(p, okr::launch_mc_scan(p->mc_cnt, mg, p->mc_tile, p->stream));
     if (max_tris > 0)
-      OKR_HIP(p, okr::launch_mc_emit(d_volume, (int)nx, (int)ny, nblk, (int)nseg, iso, p->mc_tab,
-                                     p->mc_off, d_tris, (long long*)d_cube, (long long)max_tris,
+      OKR_HIP(p, okr::launch_mc_emit(d_volume, (int)nx, (int)ny, mg, iso, p->mc_tab, p->mc_cnt,
+                                     p->mc_tile, d_tris, (long long*)d_cube, (long long)max_tris,
                                      p->stream));
   }
-  OKR_HIP(p, hipMemcpyAsync(&total, p->mc_off + nblk, sizeof(total), hipMemcpyDeviceToHost,
+  OKR_HIP(p, hipMemcpyAsync(&total, p->mc_tile + mg.ntile, sizeof(total), hipMemcpyDeviceToHost,
                             p->stream));
   OKR_HIP(p, hipStreamSynchronize(p->stream));
   *n_tris = (int64_t)total;

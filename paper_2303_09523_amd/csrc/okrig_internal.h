@@ -138,19 +138,28 @@ hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume,
 
 // ---- marching cubes (mcubes_table.cpp, kernels_mcubes.hip) ----
 constexpr int kMcMaxTri = 5;     // triangles of one cube configuration, at most
-constexpr int kMcRun = 1024;     // cubes of one (z, y) row per workgroup
+constexpr int kMcRows = 64;      // rows of one wave's strip of 64 cubes (at most 64)
+constexpr int kMcGroup = 4;      // rows whose loads the count pass issues together
 struct McTable {
   uint8_t ntri[256];                  // triangles of configuration cfg
   uint8_t tri[256][3 * kMcMaxTri];    // their cube edges, three per triangle
 };
 const McTable& mc_table();            // built once on the host
-// Workgroups: ((nz-1)(ny-1) rows) x nseg runs, nseg = ceil((nx-1) / kMcRun).
-hipError_t launch_mc_count(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
-                           const McTable* table, uint32_t* block_tris, hipStream_t s);
-hipError_t launch_mc_scan(const uint32_t* block_tris, long long nblk, unsigned long long* off,
+// Work decomposition: waves over (z-slab, run of kMcRows rows, strip of 64
+// cubes); one count per (row, strip), scanned in tiles of 1024.
+struct McGrid {
+  long long nstrip, nych, nwaves, ncnt, ntile;
+};
+McGrid mc_grid(long long nz, long long ny, long long nx);
+hipError_t launch_mc_count(const float* vol, int nx, int ny, const McGrid& g, float iso,
+                           const McTable* table, uint32_t* cnt, hipStream_t s);
+// counts -> offsets within their tile (in place); tile[0..ntile) the tiles'
+// offsets, tile[ntile] the total
+hipError_t launch_mc_scan(uint32_t* cnt, const McGrid& g, unsigned long long* tile,
                           hipStream_t s);
-hipError_t launch_mc_emit(const float* vol, int nx, int ny, long long nblk, int nseg, float iso,
-                          const McTable* table, const unsigned long long* off, float* tris,
-                          long long* cube_id, long long max_tris, hipStream_t s);
+hipError_t launch_mc_emit(const float* vol, int nx, int ny, const McGrid& g, float iso,
+                          const McTable* table, const uint32_t* off_local,
+                          const unsigned long long* tile_off, float* tris, long long* cube_id,
+                          long long max_tris, hipStream_t s);
 
 }  // namespace okr
