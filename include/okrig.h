@@ -242,8 +242,8 @@ okr_status okr_krige_points(okr_plan* plan, const okr_variogram* vario, int64_t 
  * (d_tris may then be NULL) only the count is taken; otherwise the first
  * min(total, max_tris) triangles are written and OKR_E_CAPACITY is returned if
  * total > max_tris. Non-finite values give NaN coordinates on their edges.
- * Synchronises the plan's stream; the workspace (4 KB table and 12 bytes per
- * 1024 cubes of a row) is allocated by the first call. */
+ * Synchronises the plan's stream; the workspace (a 4 KB table and 4 bytes per
+ * 64 cubes of a row) is allocated by the first call. */
 okr_status okr_marching_cubes(okr_plan* plan, const float* d_volume, float iso, float* d_tris,
                               int64_t* d_cube, int64_t max_tris, int64_t* n_tris);
 
