@@ -34,6 +34,10 @@ CASES = [
     ("edge_r2_f5", 3, 29, 70, 5, 2, "exponential", 0.02, 2.0, 4.0, True, 8),
     ("r0_f2", 4, 17, 19, 2, 0, "spherical", 0.0, 1.0, 4.0, False, 9),
     ("tiny_image", 3, 2, 3, 4, 3, "exponential", 0.01, 1.0, 6.0, True, 10),
+    # largest systems: full 7x7x2 windows with the most targets (f = 15, sixteen
+    # border rows: the last block holds no data column; unmasked, so interior
+    # systems keep all 98 candidates and need NB = 8)
+    ("r3_f15_max", 3, 20, 22, 15, 3, "spherical", 0.01, 1.0, 8.0, False, 12),
 ]
 
 
@@ -191,7 +195,10 @@ def test_forced_fp64_fallback(monkeypatch):
     np.testing.assert_array_equal(var, s64)
 
 
-@pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
+READOUT_CASES = CASES[:4] + [CASES[7]]
+
+
+@pytest.mark.parametrize("case", READOUT_CASES, ids=[c[0] for c in READOUT_CASES])
 def test_mixed_factor_readout_only(case, oracle_cache):
     """refine_max = 0: the split-FP16 factorisation's own Schur read-out meets
     the FP32 bars; no system is marked refined."""
@@ -377,7 +384,9 @@ def test_pattern_cache_splits_exactly(case):
             assert np.abs(wp[z][m] - w64[z][m]).max() <= 1.2e-7 * sill
 
 
-DRIFT_CASES = [CASES[1], CASES[2], CASES[4], CASES[5]]
+DRIFT_CASES = [CASES[1], CASES[2], CASES[4], CASES[5],
+               # the most targets the slice predictor allows (f = 14: sixteen border rows)
+               ("r3_f14_drift", 3, 18, 21, 14, 3, "exponential", 0.01, 1.0, 6.0, False, 13)]
 
 
 @pytest.mark.parametrize("case", DRIFT_CASES, ids=[c[0] for c in DRIFT_CASES])
