@@ -2,12 +2,13 @@
 // table (mcubes_table.cpp) gives each corner configuration's triangles as
 // cube-edge triples; crossing points are interpolated on their edges.
 //
-// HBM-bound. Four launches: count, two scan levels, emit. A wave takes a
-// strip of 64 cubes of one z-slab over kMcRows rows and slides down y,
-// keeping the previous row's corner values in registers, so each cube loads
-// its four new corners (two coalesced row reads per z-level). Counts are kept
-// per (row, strip): count and emit need no workgroup barrier, and the scans
-// turn them into output offsets that keep the cube order.
+// Four launches: count, two scan levels, emit. A wave takes a strip of 64
+// cubes of one z-slab over kMcRows rows and slides down y, classifying each
+// row's four corners once (a cube's configuration joins the patterns of its
+// two rows), so each cube loads only its new row (two coalesced reads per
+// z-level). Counts are kept per (row, strip): count and emit need no
+// workgroup barrier, and the scans turn them into output offsets that keep
+// the cube order.
 #include "okrig_internal.h"
 
 namespace okr {
@@ -52,14 +53,12 @@ __device__ __forceinline__ McPair mc_load(const McStrip& m, int nx, int y) {
 // Corners c = x + 2y + 4z of the cube between rows y (lo) and y + 1 (hi);
 // bit c of the configuration set when corner c is inside (value >= iso,
 // NaN outside).
-__device__ __forceinline__ int mc_cfg(const McPair& lo, const McPair& hi, float iso,
-                                      float (&v)[8]) {
-  v[0] = lo.a; v[1] = lo.b; v[2] = hi.a; v[3] = hi.b;
-  v[4] = lo.c; v[5] = lo.d; v[6] = hi.c; v[7] = hi.d;
-  int cfg = 0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) cfg |= (v[c] >= iso) ? (1 << c) : 0;
-  return cfg;
+// A row's four corners classified once: bits 0, 1, 4, 5 (x and x + 1 at z,
+// then at z + 1); the cube between rows y and y + 1 has configuration
+// nib(y) | nib(y + 1) << 2.
+__device__ __forceinline__ int mc_nib(const McPair& r, float iso) {
+  return (r.a >= iso ? 1 : 0) | (r.b >= iso ? 2 : 0) | (r.c >= iso ? 16 : 0) |
+         (r.d >= iso ? 32 : 0);
 }
 
 // Rows y + 1 .. y + kMcGroup (those before m.y1) of the strip.
@@ -105,7 +104,7 @@ __global__ __launch_bounds__(256) void mc_count_kernel(const float* __restrict__
   if (blockIdx.x * 4ll + (threadIdx.x >> 6) >= nwaves) return;
   const McStrip m = mc_strip(vol, nx, ny, nstrip, nych);
   const bool valid = m.x < nx - 1;
-  McPair lo = valid ? mc_load(m, nx, m.y0) : McPair{0, 0, 0, 0};
+  int nlo = valid ? mc_nib(mc_load(m, nx, m.y0), iso) : 0;
   // rows in groups of kMcGroup; the next group's loads are issued before the
   // current group is classified, for memory-level parallelism
   McPair cur[kMcGroup], nxt[kMcGroup];
@@ -115,12 +114,12 @@ __global__ __launch_bounds__(256) void mc_count_kernel(const float* __restrict__
 #pragma unroll
     for (int k = 0; k < kMcGroup; ++k) {
       if (y + k < m.y1) {
-        float v[8];
-        const unsigned n = valid ? ntri[mc_cfg(lo, cur[k], iso, v)] : 0u;
+        const int nhi = mc_nib(cur[k], iso);
+        const unsigned n = valid ? ntri[nlo | (nhi << 2)] : 0u;
         const unsigned tot = mc_total(mc_bits(n));
         if ((threadIdx.x & 63) == 0)
           cnt[((long long)m.z * (ny - 1) + y + k) * m.nstrip + m.strip] = tot;
-        lo = cur[k];
+        nlo = nhi;
       }
     }
 #pragma unroll
@@ -186,66 +185,79 @@ __global__ __launch_bounds__(1024) void mc_scan_top_kernel(unsigned long long* _
   if (threadIdx.x == 0) tile_sum[ntile] = carry;
 }
 
-// Per-wave queue of the emit pass: the cubes that have triangles
-// (configuration, column and row, first output slot) and one task per
-// triangle (cube slot << 3 | triangle); the corner values are read again
-// (from cache) when the triangles are computed. Rows are appended until 64 or more
-// triangles wait; the wave then computes them one per lane, so consecutive
-// lanes write consecutive triangles. Capacity: fewer than 64 waiting plus one
-// row's at most 5 x 64.
+// Per-wave queue of the emit pass: the cubes that have triangles (first
+// output slot, column, row and configuration in one 16-byte record) and one
+// task per triangle (cube slot << 3 | triangle); the corner values are read
+// again (from cache) when the triangles are computed. Rows are appended until
+// 64 or more triangles wait; the wave then computes them, two per lane at a
+// time, so consecutive lanes write consecutive triangles. Capacity: fewer
+// than 64 waiting plus one row's at most 5 x 64.
 constexpr int kMcQCubes = 128;
 constexpr int kMcQTris = 64 + 5 * 64;
+struct McCube {
+  unsigned long long first;
+  int x;
+  int ycfg;   // row | configuration << 24
+};
 struct McQueue {
-  unsigned long long first[kMcQCubes];
-  int x[kMcQCubes], y[kMcQCubes];
-  uint8_t cfg[kMcQCubes];
+  McCube cube[kMcQCubes];
   unsigned task[kMcQTris];
 };
 
-__device__ __forceinline__ void mc_flush(McQueue& q, int ntask, const McTable& tab,
-                                         const McStrip& m, int nx, int ny, float iso,
-                                         float* __restrict__ tris,
-                                         long long* __restrict__ cube_id, long long max_tris) {
-  const int z = m.z;
-  const int lane = threadIdx.x & 63;
-  for (int t = lane; t < ntask; t += 64) {
-    const unsigned task = q.task[t];
-    const int slot = (int)(task >> 3), j = (int)(task & 7);
-    const long long o = (long long)(q.first[slot] + j);
-    if (o >= max_tris) continue;
-    const int cfg = q.cfg[slot];
-    const int x = q.x[slot], y = q.y[slot];
-    const long long r0 = (long long)y * nx + x, r1 = r0 + nx;
-    const float v[8] = {m.p0[r0], m.p0[r0 + 1], m.p0[r1], m.p0[r1 + 1],
-                        m.p1[r0], m.p1[r0 + 1], m.p1[r1], m.p1[r1 + 1]};
-    float out[9];
+// Triangle j of a queued cube: three vertices and the cube id.
+__device__ __forceinline__ void mc_triangle(const McCube& c, int j, const McTable& tab,
+                                            const McStrip& m, int nx, int ny, float iso,
+                                            float* __restrict__ tris,
+                                            long long* __restrict__ cube_id, long long max_tris) {
+  const long long o = (long long)(c.first + j);
+  if (o >= max_tris) return;
+  const int cfg = (int)((unsigned)c.ycfg >> 24), y = c.ycfg & 0xffffff, x = c.x;
+  const long long r0 = (long long)y * nx + x, r1 = r0 + nx;
+  const float v[8] = {m.p0[r0], m.p0[r0 + 1], m.p0[r1], m.p0[r1 + 1],
+                      m.p1[r0], m.p1[r0 + 1], m.p1[r1], m.p1[r1 + 1]};
+  float out[9];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int ed = tab.tri[cfg][3 * j + k];
-      const int axis = ed >> 2;
-      // lower corner of the edge: bit `axis` clear, the edge's (u, w) on the
-      // other two axes
-      const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
-      const int lc = ((ed & 1) << b0) | (((ed >> 1) & 1) << b1);
-      const int hc = lc | (1 << axis);
-      float A = v[0], B = v[0];
+  for (int k = 0; k < 3; ++k) {
+    const int ed = tab.tri[cfg][3 * j + k];
+    const int axis = ed >> 2;
+    // lower corner of the edge: bit `axis` clear, the edge's (u, w) on the
+    // other two axes
+    const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
+    const int lc = ((ed & 1) << b0) | (((ed >> 1) & 1) << b1);
+    const int hc = lc | (1 << axis);
+    float A = v[0], B = v[0];
 #pragma unroll
-      for (int c = 1; c < 8; ++c) {
-        A = lc == c ? v[c] : A;
-        B = hc == c ? v[c] : B;
-      }
-      const float tt = __fdiv_rn(iso - A, B - A);
-      float p[3] = {(float)(x + (lc & 1)), (float)(y + ((lc >> 1) & 1)),
-                    (float)(z + ((lc >> 2) & 1))};
-      p[axis] = p[axis] + tt;
-      out[3 * k + 0] = p[0];
-      out[3 * k + 1] = p[1];
-      out[3 * k + 2] = p[2];
+    for (int cc = 1; cc < 8; ++cc) {
+      A = lc == cc ? v[cc] : A;
+      B = hc == cc ? v[cc] : B;
     }
-    float* dst = tris + 9 * o;
+    const float tt = __fdiv_rn(iso - A, B - A);
+    float p[3] = {(float)(x + (lc & 1)), (float)(y + ((lc >> 1) & 1)),
+                  (float)(m.z + ((lc >> 2) & 1))};
+    p[axis] = p[axis] + tt;
+    out[3 * k + 0] = p[0];
+    out[3 * k + 1] = p[1];
+    out[3 * k + 2] = p[2];
+  }
+  float* dst = tris + 9 * o;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) dst[k] = out[k];
-    if (cube_id) cube_id[o] = ((long long)z * (ny - 1) + y) * (nx - 1) + x;
+  for (int k = 0; k < 9; ++k) dst[k] = out[k];
+  if (cube_id) cube_id[o] = ((long long)m.z * (ny - 1) + y) * (nx - 1) + x;
+}
+
+__device__ __forceinline__ void mc_flush(const McQueue& q, int ntask, const McTable& tab,
+                                      const McStrip& m, int nx, int ny, float iso,
+                                      float* __restrict__ tris,
+                                      long long* __restrict__ cube_id, long long max_tris) {
+  const int lane = threadIdx.x & 63;
+  for (int t = lane; t < ntask; t += 128) {
+    // two tasks per lane: their loads overlap
+    const bool two = t + 64 < ntask;
+    const unsigned ta = q.task[t], tb = two ? q.task[t + 64] : 0u;
+    const McCube ca = q.cube[ta >> 3];
+    const McCube cb = q.cube[tb >> 3];
+    mc_triangle(ca, (int)(ta & 7), tab, m, nx, ny, iso, tris, cube_id, max_tris);
+    if (two) mc_triangle(cb, (int)(tb & 7), tab, m, nx, ny, iso, tris, cube_id, max_tris);
   }
 }
 
@@ -274,49 +286,38 @@ __global__ __launch_bounds__(256) void mc_emit_kernel(
     row_off = tile_off[e >> 10] + off_local[e];
   }
   int ncube = 0, ntask = 0;
-  McPair lo = valid ? mc_load(m, nx, m.y0) : McPair{0, 0, 0, 0};
-  McPair hi[kMcGroup], nxt[kMcGroup];
-  mc_load_group(m, nx, m.y0, valid, hi);
-  for (int y = m.y0; y < m.y1; y += kMcGroup) {
-    mc_load_group(m, nx, y + kMcGroup, valid, nxt);
-#pragma unroll
-    for (int k = 0; k < kMcGroup; ++k) {
-      if (y + k >= m.y1) break;
-      float v[8];
-      const int cfg = valid ? mc_cfg(lo, hi[k], iso, v) : 0;
-      const int n = valid ? tab.ntri[cfg] : 0;
-      const McBits bits = mc_bits((unsigned)n);
-      const unsigned pre = mc_prefix(bits), total = mc_total(bits);
-      const unsigned r_lo =
-          __builtin_amdgcn_readlane((unsigned)(row_off & 0xffffffffu), y + k - m.y0);
-      const unsigned r_hi = __builtin_amdgcn_readlane((unsigned)(row_off >> 32), y + k - m.y0);
-      const unsigned long long rbase = ((unsigned long long)r_hi << 32) | r_lo;
-      const uint64_t has = __ballot(n > 0);
-      if (n > 0) {
-        const int slot = ncube + (int)mbcnt64(has);
-        q.first[slot] = rbase + pre;
-        q.x[slot] = m.x;
-        q.y[slot] = y + k;
-        q.cfg[slot] = (uint8_t)cfg;
-        for (int j = 0; j < n; ++j) q.task[ntask + pre + j] = ((unsigned)slot << 3) | (unsigned)j;
-      }
-      ncube += __popcll(has);
-      ntask += (int)total;
-      lo = hi[k];
-      if (ntask >= 64) {
-        __builtin_amdgcn_wave_barrier();
-        mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
-        __builtin_amdgcn_wave_barrier();
-        ncube = 0;
-        ntask = 0;
-      }
+  // row by row, the row after next prefetched; one flush site keeps the
+  // kernel small
+  int nlo = valid ? mc_nib(mc_load(m, nx, m.y0), iso) : 0;
+  McPair hi = valid ? mc_load(m, nx, m.y0 + 1) : McPair{0, 0, 0, 0};
+#pragma unroll 1
+  for (int y = m.y0; y < m.y1; ++y) {
+    const McPair nxt = (valid && y + 2 <= m.y1) ? mc_load(m, nx, y + 2) : McPair{0, 0, 0, 0};
+    const int nhi = mc_nib(hi, iso);
+    const int cfg = valid ? (nlo | (nhi << 2)) : 0;
+    const int n = valid ? tab.ntri[cfg] : 0;
+    const McBits bits = mc_bits((unsigned)n);
+    const unsigned pre = mc_prefix(bits), total = mc_total(bits);
+    const unsigned r_lo = __builtin_amdgcn_readlane((unsigned)(row_off & 0xffffffffu), y - m.y0);
+    const unsigned r_hi = __builtin_amdgcn_readlane((unsigned)(row_off >> 32), y - m.y0);
+    const unsigned long long rbase = ((unsigned long long)r_hi << 32) | r_lo;
+    const uint64_t has = __ballot(n > 0);
+    if (n > 0) {
+      const int slot = ncube + (int)mbcnt64(has);
+      q.cube[slot] = McCube{rbase + pre, m.x, y | (cfg << 24)};
+      for (int j = 0; j < n; ++j) q.task[ntask + pre + j] = ((unsigned)slot << 3) | (unsigned)j;
     }
-#pragma unroll
-    for (int k = 0; k < kMcGroup; ++k) hi[k] = nxt[k];
-  }
-  if (ntask > 0) {
-    __builtin_amdgcn_wave_barrier();
-    mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
+    ncube += __popcll(has);
+    ntask += (int)total;
+    if (ntask >= 64 || (y + 1 == m.y1 && ntask > 0)) {
+      __builtin_amdgcn_wave_barrier();
+      mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
+      __builtin_amdgcn_wave_barrier();
+      ncube = 0;
+      ntask = 0;
+    }
+    nlo = nhi;
+    hi = nxt;
   }
 }
 
