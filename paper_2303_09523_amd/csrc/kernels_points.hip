@@ -204,6 +204,11 @@ __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
 // covariances depend only on the offsets (translation invariance). Their
 // weights w_t and variances are computed once per launch in FP64 (one wave),
 // and each such system is then a gather of its values and f-1 dot products.
+// With the slice predictor (Appendix A with predictors 1 and the slice s)
+// the weights are still pure geometry: from X_1 = C^-1 1, X_s = C^-1 s and
+// X_t = C^-1 c0_t, the multipliers solve G phi = (1'X_t - 1, s'X_t - t/f) with
+// G = Q'C^-1 Q, w_t = X_t - phi_1 X_1 - phi_s X_s and
+// sigma^2 = sill - w_t'c0_t - phi_1 - phi_s t/f.
 
 // Candidate c of the window -> (dx, dy, s) with the canonical index
 // c = s W^2 + (dy + r) W + (dx + r).
@@ -238,6 +243,21 @@ __global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g
     }
     return;
   }
+  // slice of each candidate (0 lower, 1 upper) and, with the drift, X_s = C^-1 s
+  double sl[2], xs[2] = {0.0, 0.0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    int dx, dy, sc = 0;
+    if (i < n) cand_xyz(i, g, &dx, &dy, &sc);
+    sl[h] = i < n ? (double)sc : 0.0;
+  }
+  if (g.drift) {
+    double unused[2] = {0.0, 0.0};
+    xs[0] = sl[0];
+    xs[1] = sl[1];
+    subst_lds(A, n, xs, unused);
+  }
   for (int t = 1; t < g.f; ++t) {
     double b1[2], bc[2];
 #pragma unroll
@@ -256,12 +276,27 @@ __global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g
     subst_lds(A, n, b1, bc);
     const double s1 = wave_sum(b1[0] + b1[1]);
     const double sc = wave_sum(bc[0] + bc[1]);
-    const double mu = (sc - 1.0) / s1;
-    const double w0 = bc[0] - mu * b1[0], w1 = bc[1] - mu * b1[1];
+    double w0, w1, lagr;
+    if (!g.drift) {
+      const double mu = (sc - 1.0) / s1;
+      w0 = bc[0] - mu * b1[0];
+      w1 = bc[1] - mu * b1[1];
+      lagr = mu;
+    } else {
+      const double qt = (double)t / g.f;
+      const double g11 = s1, g12 = wave_sum(xs[0] + xs[1]);
+      const double g22 = wave_sum(sl[0] * xs[0] + sl[1] * xs[1]);
+      const double r1 = sc - 1.0, r2 = wave_sum(sl[0] * bc[0] + sl[1] * bc[1]) - qt;
+      const double det = g11 * g22 - g12 * g12;
+      const double p1 = (g22 * r1 - g12 * r2) / det, ps = (g11 * r2 - g12 * r1) / det;
+      w0 = bc[0] - p1 * b1[0] - ps * xs[0];
+      w1 = bc[1] - p1 * b1[1] - ps * xs[1];
+      lagr = p1 + ps * qt;
+    }
     const double wc = wave_sum(w0 * c0[0] + w1 * c0[1]);
     if (lane < n) W[(t - 1) * kMaxCand + lane] = w0;
     if (lane + 64 < n) W[(t - 1) * kMaxCand + lane + 64] = w1;
-    if (lane == 0) wvar[t - 1] = v.sill - wc - mu;
+    if (lane == 0) wvar[t - 1] = v.sill - wc - lagr;
     __builtin_amdgcn_wave_barrier();
   }
 }

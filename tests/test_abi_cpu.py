@@ -55,7 +55,7 @@ def _prob(**kw):
     (dict(min_points=19), 1), (dict(precision=7), 1), (dict(algo=3), 1),
     (dict(algo=1, precision=1), 6), (dict(refine_max=9), 1), (dict(refine_tol=-1.0), 1),
     (dict(drift=2), 1), (dict(drift=1, algo=1), 6), (dict(drift=1, precision=1, refine_max=1), 6),
-    (dict(drift=1, algo=2), 6), (dict(drift=1, upsample=15), 2),
+    (dict(drift=1, upsample=15), 2),
     (dict(nx=65535, ny=65535, nslices=3), 2),
 ])
 def test_plan_validation_before_device(lib, kw, code):

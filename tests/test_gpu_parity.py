@@ -421,6 +421,37 @@ def test_drift_vs_oracle(case, precision, oracle_cache):
         assert nw <= NORMWISE_FP32
 
 
+# unmasked cases: full windows exist (with the random edges of the masked ones
+# they may not)
+@pytest.mark.parametrize("case", [CASES[0], CASES[5], DRIFT_CASES[-1]],
+                         ids=[CASES[0][0], CASES[5][0], DRIFT_CASES[-1][0]])
+@pytest.mark.parametrize("precision", ["fp32", "mixed_fp16"])
+def test_pattern_cache_drift_vs_oracle(case, precision, oracle_cache):
+    """The full-window weights of the slice-predictor form, cached in FP64,
+    and the batched path for the other systems, against the oracle."""
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    key = name + "/drift"
+    if key not in oracle_cache:
+        s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+        vol, var, _ = O.krige_volume(s, e, f, r, (model, nug, sill, rng_),
+                                     min_points=min(4, 2 * (2 * r + 1) ** 2), drift="linear_z")
+        oracle_cache[key] = (s, e, vol, var)
+    s, e, vol_o, var_o = oracle_cache[key]
+    vol, var, _, st = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision=precision,
+                              algo="pattern", min_points=min(4, 2 * (2 * r + 1) ** 2),
+                              drift="linear_z", refine_max=0)
+    np.testing.assert_array_equal(vol[::f], s)
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    ee = rel_err_est(vol[kz], vol_o[kz], np.abs(s).max())
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    print(f"case {name} pattern drift {precision}: est {ee.max():.3e} var {ev.max():.3e}",
+          flush=True)
+    assert st["bucket"][2 * (2 * r + 1) ** 2] > 0
+    assert ee.max() <= TOL["fp32"]
+    assert ev.max() <= 1e-5
+
+
 def test_drift_reproduces_linear_trend_gpu():
     """A field linear across the gap is reproduced at every target."""
     n, ny, nx, f, r = 4, 21, 23, 4, 2
