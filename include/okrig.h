@@ -124,8 +124,7 @@ typedef struct {
                            predictor). 1: universal kriging with a linear trend
                            across the gap: Appendix A with the predictors 1 and
                            the point's slice (0 lower, 1 upper; t/f at target
-                           t). Needs BATCHED or PATTERN_CACHE and, for
-                           MIXED_*, refine_max = 0;
+                           t). Needs BATCHED or PATTERN_CACHE;
                            upsample <= 14. Systems always hold points of both
                            slices (the centres are always kept), so the
                            extended system is regular. */

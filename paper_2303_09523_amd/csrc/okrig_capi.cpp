@@ -161,11 +161,8 @@ okr_status validate_problem(const okr_problem* p, std::string* msg) {
     *msg = "drift must be 0 (ordinary kriging) or 1 (slice predictor)";
     return OKR_E_INVALID_ARG;
   }
-  if (p->drift && (p->algo == OKR_ALGO_PLAIN_PER_VOXEL ||
-                   ((p->precision == OKR_MIXED_FP16 || p->precision == OKR_MIXED_BF16) &&
-                    p->refine_max > 0))) {
-    *msg = "the slice predictor needs the batched or pattern-cache algorithm and, for mixed "
-           "precisions, refine_max 0";
+  if (p->drift && p->algo == OKR_ALGO_PLAIN_PER_VOXEL) {
+    *msg = "the slice predictor needs the batched or pattern-cache algorithm";
     return OKR_E_UNSUPPORTED;
   }
   if (p->drift && p->upsample > okr::kMaxUpsample - 1) {

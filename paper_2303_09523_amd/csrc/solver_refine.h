@@ -302,8 +302,9 @@ __device__ __forceinline__ float wave_max_abs(float x) {
 
 // One system with the FP64-corrected estimate (see kernels_mixed.hip).
 constexpr int kRowTargets = 3;   // targets whose solution rows are staged at once
+constexpr int kSlotXs = 2 + kRowTargets;
 struct MixedScratch {
-  float x[2 + kRowTargets][128];   // x_1, x_z, then x_t of up to kRowTargets targets
+  float x[3 + kRowTargets][128];   // x_1, x_z, x_t of up to kRowTargets targets, x_s
   float zr[128];                   // raw data values
   double nuc[128];                 // nu_w by candidate index (0 for dropped candidates)
 };
@@ -437,17 +438,40 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
     __builtin_amdgcn_wave_barrier();
     return false;
   }
-  // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' ----
+  // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' (x_s = C^{-1} s) ----
+  // Slots of mx.x: 0 x_1, 1 x_z, 2.. the staged targets' x_t, kSlotXs x_s.
   f32x4 Z[NB];
   back_substitute<NB, UPD>(nb, Ls, Xs, ws.buf, Z);
-  write_rows<NB>(Z, ne, 2 + (ntgt < kRowTargets ? ntgt : kRowTargets), 0, mx.x);
+  const int dr = sm.bz - 1;   // 1 with the slice predictor (border rows 1, s, z, c0...)
+  const int tcnt0 = ntgt < kRowTargets ? ntgt : kRowTargets;
+  if (!dr) {
+    write_rows<NB>(Z, ne, 2 + tcnt0, 0, mx.x);
+  } else {
+    write_rows<NB>(Z, ne, 1, 0, mx.x);
+    write_rows<NB>(Z, ne + 1, 1, kSlotXs, mx.x);
+    write_rows<NB>(Z, ne + 2, 1 + tcnt0, 1, mx.x);
+  }
   const double x1_0 = p0 < n ? (double)mx.x[0][p0] : 0.0, x1_1 = p1 < n ? (double)mx.x[0][p1] : 0.0;
   const double xz_0 = p0 < n ? (double)mx.x[1][p0] : 0.0, xz_1 = p1 < n ? (double)mx.x[1][p1] : 0.0;
-  double s01[2] = {x1_0 + x1_1, xz_0 + xz_1};
-  wave_sums(s01);
-  const double g11 = s01[0];
-  const double nu_mu = s01[1] / g11;
-  const double nu0 = xz_0 - nu_mu * x1_0, nu1 = xz_1 - nu_mu * x1_1;
+  const double xs_0 = (dr && p0 < n) ? (double)mx.x[kSlotXs][p0] : 0.0;
+  const double xs_1 = (dr && p1 < n) ? (double)mx.x[kSlotXs][p1] : 0.0;
+  const double sl_0 = (dr && p0 < n) ? (double)((ws.desc[p0] >> 14) & 1) : 0.0;
+  const double sl_1 = (dr && p1 < n) ? (double)((ws.desc[p1] >> 14) & 1) : 0.0;
+  // multipliers of the adjoint system: OK nu_mu = 1'x_z / 1'x_1; with the
+  // slice predictor G (nu_1, nu_s) = (1'x_z, s'x_z), G = Q'C^-1 Q
+  double g[5] = {x1_0 + x1_1, xz_0 + xz_1, xs_0 + xs_1, sl_0 * xs_0 + sl_1 * xs_1,
+                 sl_0 * xz_0 + sl_1 * xz_1};
+  wave_sums(g);
+  const double g11 = g[0], g1s = g[2], gss = g[3];
+  const double det = g11 * gss - g1s * g1s;
+  double nu_1, nu_s = 0.0;
+  if (!dr) {
+    nu_1 = g[1] / g11;
+  } else {
+    nu_1 = (gss * g[1] - g1s * g[4]) / det;
+    nu_s = (g11 * g[4] - g1s * g[1]) / det;
+  }
+  const double nu0 = xz_0 - nu_1 * x1_0 - nu_s * xs_0, nu1 = xz_1 - nu_1 * x1_1 - nu_s * xs_1;
   mx.nuc[lane] = 0.0;
   mx.nuc[lane + 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
@@ -455,48 +479,66 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   if (p1 < n) mx.nuc[ws.desc[p1] & 0x7f] = nu1;
   __builtin_amdgcn_wave_barrier();
   // ---- 4. FP64 correction ----
-  // With h = z' - C nu_w - nu_mu 1 (the FP64 residual of the adjoint system)
-  // and w_t = x_t - mu_t x_1,  z'w_t + nu'(r_t - K lambda_t) equals
-  //   A_t - mu_t B + nu_mu,  A_t = h'x_t + nu_w'c0_t,  B = h'x_1 + 1'nu_w.
+  // With h = z' - C nu_w - Q nu_phi (the FP64 residual of the adjoint system)
+  // and w_t = x_t - x_Q phi_t, z'w_t + nu'(r_t - K lambda_t) equals
+  //   A_t - phi_t'B + nu_phi'q0_t,  A_t = h'x_t + nu_w'c0_t,  B = x_Q'h + Q'nu_w
+  // (OK: Q = 1, phi_t = mu_t; with the slice predictor Q = [1 s], q0_t = (1, t/f)).
   double cn0, cn1;
   matvec64(n, ncand, ws.desc, mx.nuc, ms, cn0, cn1);
   const double zd = (double)zref;
   const double sd = ldexp(1.0, ex);
   const double isd = ldexp(1.0, -ex);
-  const double h0 = p0 < n ? ((double)mx.zr[p0] - zd) * isd - cn0 - nu_mu : 0.0;
-  const double h1 = p1 < n ? ((double)mx.zr[p1] - zd) * isd - cn1 - nu_mu : 0.0;
+  const double h0 = p0 < n ? ((double)mx.zr[p0] - zd) * isd - cn0 - nu_1 - nu_s * sl_0 : 0.0;
+  const double h1 = p1 < n ? ((double)mx.zr[p1] - zd) * isd - cn1 - nu_1 - nu_s * sl_1 : 0.0;
   const int d0 = p0 < n ? ws.desc[p0] : 0, d1 = p1 < n ? ws.desc[p1] : 0;
-  double B = 0.0;
+  double B1 = 0.0, Bs = 0.0;
   for (int t0 = 1; t0 <= ntgt; t0 += kRowTargets) {
     const int cnt = (ntgt - t0 + 1) < kRowTargets ? (ntgt - t0 + 1) : kRowTargets;
-    if (t0 > 1) write_rows<NB>(Z, ne + 1 + t0, cnt, 2, mx.x);
-    double s[2 * kRowTargets + 1];
+    if (t0 > 1) write_rows<NB>(Z, ne + sm.bz + t0, cnt, 2, mx.x);
+    double s[3 * kRowTargets + 2];
 #pragma unroll
     for (int k = 0; k < kRowTargets; ++k) {
-      s[2 * k] = 0.0;
-      s[2 * k + 1] = 0.0;
+      s[3 * k] = 0.0;
+      s[3 * k + 1] = 0.0;
+      s[3 * k + 2] = 0.0;
       if (k < cnt) {
         const int t = t0 + k;
         const double xt0 = p0 < n ? (double)mx.x[2 + k][p0] : 0.0;
         const double xt1 = p1 < n ? (double)mx.x[2 + k][p1] : 0.0;
         const double c00 = p0 < n ? ms.t064[(t - 1) * kT0Stride + (d0 >> 16)] : 0.0;
         const double c01 = p1 < n ? ms.t064[(t - 1) * kT0Stride + (d1 >> 16)] : 0.0;
-        s[2 * k] = xt0 + xt1;
-        s[2 * k + 1] = (h0 * xt0 + h1 * xt1) + (nu0 * c00 + nu1 * c01);
+        s[3 * k] = xt0 + xt1;
+        s[3 * k + 1] = (h0 * xt0 + h1 * xt1) + (nu0 * c00 + nu1 * c01);
+        s[3 * k + 2] = sl_0 * xt0 + sl_1 * xt1;
       }
     }
-    s[2 * kRowTargets] = t0 == 1 ? (h0 * x1_0 + h1 * x1_1) + (nu0 + nu1) : 0.0;
+    s[3 * kRowTargets] = t0 == 1 ? (h0 * x1_0 + h1 * x1_1) + (nu0 + nu1) : 0.0;
+    s[3 * kRowTargets + 1] = (t0 == 1 && dr) ? (h0 * xs_0 + h1 * xs_1) + (sl_0 * nu0 + sl_1 * nu1)
+                                             : 0.0;
     wave_sums(s);
-    if (t0 == 1) B = s[2 * kRowTargets];
+    if (t0 == 1) {
+      B1 = s[3 * kRowTargets];
+      Bs = s[3 * kRowTargets + 1];
+    }
 #pragma unroll
     for (int k = 0; k < kRowTargets; ++k) {
       if (k < cnt) {
         const int t = t0 + k;
-        const double mu = (s[2 * k] - 1.0) / g11;
-        if (lane == t - 1) *est_out = zd + sd * (s[2 * k + 1] - mu * B + nu_mu);
+        double p1c, psc = 0.0, corr;
+        if (!dr) {
+          p1c = (s[3 * k] - 1.0) / g11;
+          corr = s[3 * k + 1] - p1c * B1 + nu_1;
+        } else {
+          const double qt = (double)t / (ntgt + 1);
+          const double r1 = s[3 * k] - 1.0, r2 = s[3 * k + 2] - qt;
+          p1c = (gss * r1 - g1s * r2) / det;
+          psc = (g11 * r2 - g1s * r1) / det;
+          corr = s[3 * k + 1] - p1c * B1 - psc * Bs + nu_1 + nu_s * qt;
+        }
+        if (lane == t - 1) *est_out = zd + sd * corr;
         if (w_out && t == 1) {
-          if (p0 < n) w_out[p0] = (double)mx.x[2][p0] - mu * x1_0;
-          if (p1 < n) w_out[p1] = (double)mx.x[2][p1] - mu * x1_1;
+          if (p0 < n) w_out[p0] = (double)mx.x[2][p0] - p1c * x1_0 - psc * xs_0;
+          if (p1 < n) w_out[p1] = (double)mx.x[2][p1] - p1c * x1_1 - psc * xs_1;
         }
       }
     }

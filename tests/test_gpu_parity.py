@@ -421,6 +421,33 @@ def test_drift_vs_oracle(case, precision, oracle_cache):
         assert nw <= NORMWISE_FP32
 
 
+@pytest.mark.parametrize("case", DRIFT_CASES, ids=[c[0] for c in DRIFT_CASES])
+def test_drift_fp64_correction_vs_oracle(case, oracle_cache):
+    """The mixed FP16 factorisation with the FP64 correction in the
+    slice-predictor form (two multipliers) reaches the corrected path's bar."""
+    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
+    key = name + "/drift"
+    if key not in oracle_cache:
+        s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
+        vol, var, _ = O.krige_volume(s, e, f, r, (model, nug, sill, rng_),
+                                     min_points=min(4, 2 * (2 * r + 1) ** 2), drift="linear_z")
+        oracle_cache[key] = (s, e, vol, var)
+    s, e, vol_o, var_o = oracle_cache[key]
+    vol, var, fl, st = run_gpu(s, e, f, r, (model, nug, sill, rng_), precision="mixed_fp16",
+                               min_points=min(4, 2 * (2 * r + 1) ** 2), drift="linear_z",
+                               refine_max=1, refine_tol=0.0, flags=True)
+    np.testing.assert_array_equal(vol[::f], s)
+    kz = np.ones(vol.shape[0], bool)
+    kz[::f] = False
+    ee = rel_err_est(vol[kz], vol_o[kz], np.abs(s).max())
+    ev = rel_err_var(var[kz], var_o[kz], sill)
+    print(f"case {name} drift corrected: est {ee.max():.3e} var {ev.max():.3e} "
+          f"refined {st['n_refined']}", flush=True)
+    assert st["n_refined"] + st["n_fp64_fallback"] == (n - 1) * ny * nx
+    assert ee.max() <= TOL["mixed_fp16"]
+    assert ev.max() <= 1e-5
+
+
 # unmasked cases: full windows exist (with the random edges of the masked ones
 # they may not)
 @pytest.mark.parametrize("case", [CASES[0], CASES[5], DRIFT_CASES[-1]],
