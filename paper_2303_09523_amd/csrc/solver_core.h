@@ -137,29 +137,24 @@ __device__ __forceinline__ int pair_class(int dp, int dq) {
   return ((cp ^ cq) & 64) | ((ddy < 0 ? -ddy : ddy) << 3) | (ddx < 0 ? -ddx : ddx);
 }
 
-// -Cov of two data points: FP32 from the pair table, FP64 from the class table
-// through the pair-class byte table (offsets from cc_row / cc_col).
+// -Cov of two data points (FP64 path): the class table through the pair-class
+// byte table (offsets from cc_row / cc_col). FP32 blocks assemble their
+// entries with tile_f32 below.
 template <typename T>
 __device__ __forceinline__ T neg_cov_pair(int dp, int dq, int rbase, int col, const Smem<T>& sm);
-template <>
-__device__ __forceinline__ float neg_cov_pair<float>(int, int, int rbase, int col,
-                                                     const Smem<float>& sm) {
-  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(sm.cc) + rbase + col);
-}
 template <>
 __device__ __forceinline__ double neg_cov_pair<double>(int, int, int rbase, int col,
                                                        const Smem<double>& sm) {
   return sm.tc[sm.cls[rbase + col]];
 }
 
-// Offsets of a descriptor's row and column in the pair tables (0 for rows and
-// columns that are not data points, which never read them): bytes into the
-// FP32 covariance table, entries of the FP64 class table.
+// Offsets of a descriptor's row and column in the pair-class byte table (0
+// for rows and columns that are not data points, which never read them).
 template <typename T> __device__ __forceinline__ int cc_row(int d, int ncand) {
-  return d >= 0 ? (d & 0x7f) * ncand * (sizeof(T) == 4 ? 4 : 1) : 0;
+  return d >= 0 ? (d & 0x7f) * ncand : 0;
 }
 template <typename T> __device__ __forceinline__ int cc_col(int d) {
-  return d >= 0 ? (d & 0x7f) * (sizeof(T) == 4 ? 4 : 1) : 0;
+  return d >= 0 ? (d & 0x7f) : 0;
 }
 
 // ---- FP32 entries without branches ----
@@ -238,7 +233,8 @@ __device__ __forceinline__ f32x4 tile_f32(int i, int j, int n, int bstart, const
   return t;
 }
 
-// Entry -M[p][q] of the augmented matrix from the two indices' descriptors:
+// Entry -M[p][q] of the augmented matrix (FP64 path) from the two indices'
+// descriptors:
 //   >= 0: data point, -1: identity padding, <= -2: border row b = -2 - d.
 // Border rows: b = 0 the constant predictor, 0 < b < bz the point's slice
 // (0 lower, 1 upper; with the drift), b = bz the data values, b > bz the
@@ -290,20 +286,6 @@ __device__ __forceinline__ void schur_readout(const T* buf, int ne, int t, int d
   }
 }
 
-// Pivot of one column: records the range of pivots and replaces a pivot that
-// is not positive (NaN included) by 1 (the system is then flagged). Inputs are
-// finite (checked at placement) and scaled, so a pivot cannot overflow.
-template <typename T>
-__device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) {
-  if (!(piv > T(0))) {
-    bad = true;
-    piv = T(1);
-  }
-  minpiv = piv < minpiv ? piv : minpiv;
-  maxpiv = piv > maxpiv ? piv : maxpiv;
-  return piv;
-}
-
 // Cholesky of one diagonal tile over its first ne columns, in four panels of
 // four columns. D is the negated tile (-A); on return its lower triangle holds
 // the trailing Schur complement (negated) of the columns >= ne, and X holds
@@ -312,6 +294,9 @@ __device__ __forceinline__ T take_pivot(T piv, T& minpiv, T& maxpiv, bool& bad) 
 // eliminated one by one on the vector ALUs; the rest of the tile then takes
 // the panel's rank-4 update with one MFMA (and one more for X), instead of
 // four rank-1 MFMAs. Entries above the diagonal are not kept up to date.
+// The range of the pivots is recorded, and a pivot that is not positive (NaN
+// included) is replaced by 1 and the system flagged; inputs are finite
+// (checked at placement) and scaled, so a pivot cannot overflow.
 //
 // FP32 pivots are uniform values; positive finite floats order like their bit
 // patterns, so the check and the running range run on the scalar unit.
