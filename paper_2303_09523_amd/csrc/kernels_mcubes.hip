@@ -204,6 +204,15 @@ struct McQueue {
   unsigned task[kMcQTris];
 };
 
+// v[c] for a lane-varying corner c: a select tree on the bits of c.
+__device__ __forceinline__ float mc_pick(const float (&v)[8], int c) {
+  const bool b0 = c & 1, b1 = c & 2, b2 = c & 4;
+  const float q0 = b0 ? v[1] : v[0], q1 = b0 ? v[3] : v[2];
+  const float q2 = b0 ? v[5] : v[4], q3 = b0 ? v[7] : v[6];
+  const float r0 = b1 ? q1 : q0, r1 = b1 ? q3 : q2;
+  return b2 ? r1 : r0;
+}
+
 // Triangle j of a queued cube: three vertices and the cube id.
 __device__ __forceinline__ void mc_triangle(const McCube& c, int j, const McTable& tab,
                                             const McStrip& m, int nx, int ny, float iso,
@@ -225,12 +234,7 @@ __device__ __forceinline__ void mc_triangle(const McCube& c, int j, const McTabl
     const int b0 = axis == 0 ? 1 : 0, b1 = axis == 2 ? 1 : 2;
     const int lc = ((ed & 1) << b0) | (((ed >> 1) & 1) << b1);
     const int hc = lc | (1 << axis);
-    float A = v[0], B = v[0];
-#pragma unroll
-    for (int cc = 1; cc < 8; ++cc) {
-      A = lc == cc ? v[cc] : A;
-      B = hc == cc ? v[cc] : B;
-    }
+    const float A = mc_pick(v, lc), B = mc_pick(v, hc);
     const float tt = __fdiv_rn(iso - A, B - A);
     float p[3] = {(float)(x + (lc & 1)), (float)(y + ((lc >> 1) & 1)),
                   (float)(m.z + ((lc >> 2) & 1))};
