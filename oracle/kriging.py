@@ -380,26 +380,38 @@ def _loso_systems(slices, r, held):
     return hs, ys, xs
 
 
-def loso_loss(slices, r: int, vario, min_points: int = 4):
+def loso_loss(slices, r: int, vario, min_points: int = 4, edges=None, drift: str = "none"):
     """Mean over held-out slices s = 1..n-2 and all their voxels of
-    (z_hat - z)^2, z_hat kriged from slices s-1 and s+1."""
+    (z_hat - z)^2, z_hat kriged from slices s-1 and s+1 (edge masks of those
+    two slices when given; ordinary kriging or the slice predictor)."""
     vario = _vtuple(vario)
     slices = np.asarray(slices, dtype=np.float32)
     ns = slices.shape[0]
     hs, ys, xs = _loso_systems(slices, r, range(1, ns - 1))
-    est, _, _, _ = _systems(slices[hs - 1], slices[hs + 1], None, None, ys, xs, 2, [1], r, vario,
-                            min_points)
+    elo = ehi = None
+    if edges is not None:
+        edges = np.asarray(edges, dtype=np.uint8)
+        elo, ehi = edges[hs - 1], edges[hs + 1]
+    est, _, _, _ = _systems(slices[hs - 1], slices[hs + 1], elo, ehi, ys, xs, 2, [1], r, vario,
+                            min_points, drift=drift)
     truth = slices[hs, ys, xs].astype(np.float64)
     return float(np.mean((est[:, 0] - truth) ** 2))
 
 
-def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192):
+def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192, edges=None,
+                   drift: str = "none"):
     """Loss and its FP64 adjoint gradient d L / d(nugget, sill, range).
 
-    Per system, with K the bordered matrix and lambda = [w; mu]:
-    nu = K^{-1} [e z_nb; 0], e = 2 (z_hat - z) / N, and
+    Per system, with K the matrix of Appendix A's extended system (border Q:
+    the constant predictor, with drift="linear_z" also the point's slice, 0
+    lower and 1 upper; target row q0 = (1[, 1/2])) and lambda = [w; phi]:
+    nu = K^{-1} [e z_nb; 0], e = 2 (z_hat - z) / N, and, since Q and q0 do
+    not depend on the variogram,
     dL/dtheta = nu_w^T dc0/dtheta - nu_w^T (dC/dtheta) w.
+    The centre column of both slices is always kept, so Q has full rank.
     """
+    if drift not in ("none", "linear_z"):
+        raise ValueError(drift)
     model, nug, sill, a = _vtuple(vario)
     slices = np.asarray(slices, dtype=np.float32)
     ns, H, Wd = slices.shape
@@ -413,7 +425,10 @@ def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192
     for c_ in range(0, N, chunk):
         sl = slice(c_, min(N, c_ + chunk))
         hc, yc, xc = hs[sl], ys[sl], xs[sl]
-        kept, _ = select_neighbours(None, yc, xc, r, min_points, (H, Wd))
+        ep = None
+        if edges is not None:
+            ep = (np.asarray(edges[hc - 1], dtype=np.uint8), np.asarray(edges[hc + 1], dtype=np.uint8))
+        kept, _ = select_neighbours(ep, yc, xc, r, min_points, (H, Wd))
         n_sys = kept.sum(axis=1)
         for n in np.unique(n_sys):
             grp = np.nonzero(n_sys == n)[0]
@@ -424,16 +439,24 @@ def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192
             C = covariance(model, nug, sill, a, d)
             c0 = covariance(model, nug, sill, a, d0)
             G = len(grp)
-            K = np.zeros((G, n + 1, n + 1))
+            dx_, dy_, s_ = cands[ci, 0], cands[ci, 1], cands[ci, 2]
+            if drift == "none":
+                Q = np.ones((G, n, 1))
+                q0 = np.array([1.0])
+            else:
+                assert np.all(s_.min(axis=1) == 0) and np.all(s_.max(axis=1) == 1)
+                Q = np.stack([np.ones((G, n)), s_.astype(np.float64)], axis=2)
+                q0 = np.array([1.0, 0.5])
+            p_ = Q.shape[2]
+            K = np.zeros((G, n + p_, n + p_))
             K[:, :n, :n] = C
-            K[:, :n, n] = 1.0
-            K[:, n, :n] = 1.0
-            rhs = np.zeros((G, n + 1))
+            K[:, :n, n:] = Q
+            K[:, n:, :n] = np.transpose(Q, (0, 2, 1))
+            rhs = np.zeros((G, n + p_))
             rhs[:, :n] = c0
-            rhs[:, n] = 1.0
+            rhs[:, n:] = q0
             lam = np.linalg.solve(K, rhs[:, :, None])[:, :, 0]
             w = lam[:, :n]
-            dx_, dy_, s_ = cands[ci, 0], cands[ci, 1], cands[ci, 2]
             src_lo = slices[hc[grp] - 1]
             src_hi = slices[hc[grp] + 1]
             gi = np.arange(G)[:, None]
@@ -445,7 +468,7 @@ def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192
             res = est - truth
             loss += float(np.sum(res ** 2))
             e = 2.0 * res / N
-            adj_rhs = np.zeros((G, n + 1))
+            adj_rhs = np.zeros((G, n + p_))
             adj_rhs[:, :n] = e[:, None] * z
             nu = np.linalg.solve(K, adj_rhs[:, :, None])[:, :, 0]
             nu_w = nu[:, :n]
@@ -456,7 +479,8 @@ def loso_loss_grad(slices, r: int, vario, min_points: int = 4, chunk: int = 8192
     return loss / N, grad
 
 
-def loso_fd_grad(slices, r: int, vario, h: float = 1e-4, min_points: int = 4):
+def loso_fd_grad(slices, r: int, vario, h: float = 1e-4, min_points: int = 4, edges=None,
+                 drift: str = "none"):
     """Central finite differences of loso_loss on raw (nugget, sill, range)."""
     model, nug, sill, a = _vtuple(vario)
     th = np.array([nug, sill, a], dtype=np.float64)
@@ -465,8 +489,8 @@ def loso_fd_grad(slices, r: int, vario, h: float = 1e-4, min_points: int = 4):
         tp, tm = th.copy(), th.copy()
         tp[k] += h
         tm[k] -= h
-        lp = loso_loss(slices, r, (model, *tp), min_points)
-        lm = loso_loss(slices, r, (model, *tm), min_points)
+        lp = loso_loss(slices, r, (model, *tp), min_points, edges, drift)
+        lm = loso_loss(slices, r, (model, *tm), min_points, edges, drift)
         g[k] = (lp - lm) / (2 * h)
     return g
 

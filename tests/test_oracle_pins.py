@@ -352,6 +352,55 @@ def test_P14_adjoint_vs_finite_differences():
     assert abs(0.1 * g[0] + 1.0 * g[1]) <= 1e-12 * np.abs(g).max()
 
 
+def _loso_edges(shape, seed, frac=0.2):
+    return (np.random.default_rng(seed).random(shape) < frac).astype(np.uint8)
+
+
+def test_P14_drift_adjoint_with_edges_vs_finite_differences():
+    vario = W.Variogram("exponential", 0.02, 0.8, 5.0)
+    f, _ = W.gaussian_field((5, 12, 11), vario, seed=5)
+    s = f.astype(np.float32)
+    e = _loso_edges(s.shape, 6)
+    th = ("exponential", 0.1, 1.0, 2.0)
+    for drift in ("none", "linear_z"):
+        L, g = O.loso_loss_grad(s, 2, th, edges=e, drift=drift)
+        assert L == pytest.approx(O.loso_loss(s, 2, th, edges=e, drift=drift), rel=1e-13)
+        fd = O.loso_fd_grad(s, 2, th, h=1e-4, edges=e, drift=drift)
+        np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-12 * np.abs(g).max())
+        # Q and q0 do not scale with C: the weights still depend on nugget/sill
+        # and range only
+        assert abs(0.1 * g[0] + 1.0 * g[1]) <= 1e-12 * np.abs(g).max()
+
+
+def test_P14_drift_reproduces_a_trend_across_slices():
+    # a field constant in-plane and linear across the slices: with edge masks
+    # the two slices keep different point sets, so ordinary kriging's weights
+    # on the upper slice no longer sum to 1/2 and it misses the trend, while
+    # the slice predictor reproduces it exactly
+    ns, ny, nx = 5, 10, 9
+    s = np.broadcast_to((3.0 + 2.0 * np.arange(ns, dtype=np.float32))[:, None, None],
+                        (ns, ny, nx)).astype(np.float32)
+    e = _loso_edges(s.shape, 8, 0.3)
+    th = ("spherical", 0.05, 1.0, 4.0)
+    L_ok = O.loso_loss(s, 2, th, edges=e)
+    L_dr, g_dr = O.loso_loss_grad(s, 2, th, edges=e, drift="linear_z")
+    assert L_ok > 1e-3
+    assert L_dr < 1e-20 and np.abs(g_dr).max() < 1e-9
+
+
+def test_P14_drift_equals_ordinary_kriging_without_masks():
+    # without masks both slices keep mirror-image point sets around a target
+    # half-way between them, so ordinary kriging already puts weight 1/2 on
+    # each slice and the slice constraint changes nothing
+    rng = np.random.default_rng(9)
+    s = rng.normal(size=(4, 9, 10)).astype(np.float32)
+    th = ("gaussian", 0.1, 1.0, 3.0)
+    L0, g0 = O.loso_loss_grad(s, 2, th)
+    L1, g1 = O.loso_loss_grad(s, 2, th, drift="linear_z")
+    assert L1 == pytest.approx(L0, rel=1e-10)
+    np.testing.assert_allclose(g1, g0, rtol=1e-7, atol=1e-12 * np.abs(g0).max())
+
+
 @pytest.mark.parametrize("model", ["spherical", "gaussian"])
 def test_P14_adjoint_other_models(model):
     rng = np.random.default_rng(12)
