@@ -193,13 +193,17 @@ okr_status okr_select(okr_plan* plan, const uint8_t* d_edge, uint64_t* d_bits, u
  * 1..nslices-2 is predicted from slices s-1 and s+1 (at distance 1 each, the
  * geometry of upsample 2) with the plan's window and edge rule, and
  * *d_loss (device double) receives the mean of (z_hat - z)^2 over all those
- * voxels. Requires a plan with upsample == 2 and nslices >= 3. */
+ * voxels. With a drift plan (problem.drift = 1) the predictions use the
+ * slice predictor as the volume path does (q0 = (1, 1/2)). Requires a plan
+ * with upsample == 2, nslices >= 3 and a batched algorithm. */
 okr_status okr_loso_forward(okr_plan* plan, const okr_variogram* vario, const float* d_slices,
                             const uint8_t* d_edge, double* d_loss);
 
 /* Gradient of the last okr_loso_forward loss on this plan with respect to
- * (nugget, sill, range), by the adjoint of the bordered system:
- * nu = K^{-1} [e z; 0], dL/dtheta = nu_w^T dc0/dtheta - nu_w^T dC/dtheta w.
+ * (nugget, sill, range), by the adjoint of the extended system of
+ * Appendix A, K = [[C, Q], [Q^T, 0]] (Q = 1, or [1 s] with the drift):
+ * nu = K^{-1} [e z; 0], dL/dtheta = nu_w^T dc0/dtheta - nu_w^T dC/dtheta w
+ * (Q does not depend on the variogram).
  * d_grad: device double[3]. OKR_E_INVALID_ARG if no forward preceded it. */
 okr_status okr_loso_backward(okr_plan* plan, double* d_grad);
 

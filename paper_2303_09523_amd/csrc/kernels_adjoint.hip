@@ -7,7 +7,9 @@
 // slice) system (FP32 factorisation, FP64-corrected estimate), residual
 // stored per system. Backward: the same solve recomputed (no factor is
 // stored), then with e = 2 (z_hat - z) / N, the weights w and the adjoint
-// vector nu = K^{-1} [e z; 0] of the bordered system K = [[C, 1], [1', 0]],
+// vector nu = K^{-1} [e z; 0] of the extended system K = [[C, Q], [Q', 0]]
+// (Q = 1, or [1 s] with the slice predictor; Q does not depend on the
+// variogram, so its derivative drops out),
 //   dL/dtheta = nu_w' dc0/dtheta - nu_w' (dC/dtheta) w
 // with dC/dtheta and dc0/dtheta from the FP64 derivative tables (FP64
 // products). Per-system values are summed in a fixed order, so the loss and

@@ -760,8 +760,6 @@ okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float
   if (!d_slices || !d_loss) return fail(p, OKR_E_INVALID_ARG, "slices and loss are required");
   if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL)
     return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out needs a batched plan");
-  if (p->geo.drift)
-    return fail(p, OKR_E_UNSUPPORTED, "leave-one-slice-out is ordinary kriging (no drift)");
   if (p->geo.f != 2)
     return fail(p, OKR_E_UNSUPPORTED,
                 "leave-one-slice-out uses the upsample-2 geometry (held-out slice half-way)");

@@ -40,6 +40,51 @@ def test_loso_loss_and_grad_vs_oracle(model, theta):
     np.testing.assert_allclose(g, g_o, rtol=1e-4, atol=1e-6 * np.abs(g_o).max())
 
 
+@pytest.mark.parametrize("drift", ["none", "linear_z"])
+@pytest.mark.parametrize("r", [2, 3])
+def test_loso_edges_and_drift_vs_oracle(r, drift):
+    """Edge masks on both neighbouring slices (so the kept sets differ and the
+    floor fills some systems), ordinary kriging and the slice predictor."""
+    import torch
+    import paper_2303_09523_amd as P
+    s = _field(5, 26, 23, seed=13)
+    e = (np.random.default_rng(14).random(s.shape) < 0.2).astype(np.uint8)
+    th = ("spherical", 0.05, 1.0, 4.5)
+    L_o, g_o = O.loso_loss_grad(s, r, th, edges=e, drift=drift)
+    n, ny, nx = s.shape
+    plan = P.Plan(nx, ny, n, 2, r, 4, drift=drift)
+    print(f"loso r={r} drift={drift}", flush=True)
+    loss = plan.loso_forward(torch.from_numpy(s).cuda(), th, torch.from_numpy(e).cuda())
+    grad = plan.loso_backward()
+    L, g = float(loss.item()), grad.cpu().numpy()
+    plan.close()
+    print(f"loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
+    assert abs(L - L_o) <= 1e-9 * abs(L_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-4, atol=1e-6 * np.abs(g_o).max())
+
+
+def test_loso_drift_reproduces_a_trend_across_slices():
+    """A field constant in-plane and linear across the slices, with masks:
+    ordinary kriging misses the trend, the slice predictor reproduces it."""
+    import torch
+    import paper_2303_09523_amd as P
+    ns, ny, nx = 5, 19, 17
+    s = np.broadcast_to((3.0 + 2.0 * np.arange(ns, dtype=np.float32))[:, None, None],
+                        (ns, ny, nx)).astype(np.float32)
+    e = (np.random.default_rng(8).random(s.shape) < 0.3).astype(np.uint8)
+    th = ("spherical", 0.05, 1.0, 4.0)
+    st, et = torch.from_numpy(s).cuda(), torch.from_numpy(e).cuda()
+    out = {}
+    for drift in ("none", "linear_z"):
+        plan = P.Plan(nx, ny, ns, 2, 2, 4, drift=drift)
+        out[drift] = float(plan.loso_forward(st, th, et).item())
+        plan.close()
+    L_ok = O.loso_loss(s, 2, th, edges=e)
+    print(out, L_ok, flush=True)
+    assert abs(out["none"] - L_ok) <= 1e-9 * L_ok and L_ok > 1e-3
+    assert out["linear_z"] < 1e-10
+
+
 def test_loso_grad_vs_gpu_finite_differences():
     import torch
     s = _field(5, 20, 22, seed=3)
