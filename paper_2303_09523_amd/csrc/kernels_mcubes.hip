@@ -7,8 +7,9 @@
 // row's four corners once (a cube's configuration joins the patterns of its
 // two rows), so each cube loads only its new row (two coalesced reads per
 // z-level). Counts are kept per (row, strip): count and emit need no
-// workgroup barrier, and the scans turn them into output offsets that keep
-// the cube order.
+// workgroup barrier, the scans turn them into output offsets that keep the
+// cube order, and the emit pass visits only the (row, strip) pairs whose
+// count is not zero.
 #include "okrig_internal.h"
 
 namespace okr {
@@ -267,9 +268,9 @@ __device__ __forceinline__ void mc_flush(const McQueue& q, int ntask, const McTa
 
 __global__ __launch_bounds__(256) void mc_emit_kernel(
     const float* __restrict__ vol, int nx, int ny, int nstrip, int nych, long long nwaves,
-    float iso, const McTable* __restrict__ table, const uint32_t* __restrict__ off_local,
-    const unsigned long long* __restrict__ tile_off, float* __restrict__ tris,
-    long long* __restrict__ cube_id, long long max_tris) {
+    long long ncnt, long long ntile, float iso, const McTable* __restrict__ table,
+    const uint32_t* __restrict__ off_local, const unsigned long long* __restrict__ tile_off,
+    float* __restrict__ tris, long long* __restrict__ cube_id, long long max_tris) {
   __shared__ McTable tab;
   __shared__ McQueue queues[4];
   {
@@ -283,22 +284,38 @@ __global__ __launch_bounds__(256) void mc_emit_kernel(
   const McStrip m = mc_strip(vol, nx, ny, nstrip, nych);
   const bool valid = m.x < nx - 1;
   const int lane = threadIdx.x & 63;
-  // output offsets of the strip's rows, one row per lane (kMcRows <= 64)
+  // output offsets of the strip's rows, one row per lane (kMcRows <= 64); a
+  // row whose offset equals the next (row, strip)'s has no triangle in this
+  // strip and is skipped
   unsigned long long row_off = 0;
+  bool row_has = false;
   if (m.y0 + lane < m.y1) {
     const long long e = ((long long)m.z * (ny - 1) + m.y0 + lane) * m.nstrip + m.strip;
     row_off = tile_off[e >> 10] + off_local[e];
+    const long long e1 = e + 1;
+    const unsigned long long next = e1 < ncnt ? tile_off[e1 >> 10] + off_local[e1] : tile_off[ntile];
+    row_has = next > row_off;
   }
+  uint64_t act = __ballot(row_has);
+  if (act == 0) return;
+  // the rows with triangles in order; the next one's corner rows are loaded
+  // while the current one is queued (a row shared by consecutive cubes' rows
+  // is loaded once); one flush site keeps the kernel small
+  int y = m.y0 + (int)__builtin_ctzll(act);
+  act &= act - 1;
+  McPair lo = valid ? mc_load(m, nx, y) : McPair{0, 0, 0, 0};
+  McPair hi = valid ? mc_load(m, nx, y + 1) : McPair{0, 0, 0, 0};
   int ncube = 0, ntask = 0;
-  // row by row, the row after next prefetched; one flush site keeps the
-  // kernel small
-  int nlo = valid ? mc_nib(mc_load(m, nx, m.y0), iso) : 0;
-  McPair hi = valid ? mc_load(m, nx, m.y0 + 1) : McPair{0, 0, 0, 0};
 #pragma unroll 1
-  for (int y = m.y0; y < m.y1; ++y) {
-    const McPair nxt = (valid && y + 2 <= m.y1) ? mc_load(m, nx, y + 2) : McPair{0, 0, 0, 0};
-    const int nhi = mc_nib(hi, iso);
-    const int cfg = valid ? (nlo | (nhi << 2)) : 0;
+  for (;;) {
+    const bool more = act != 0;
+    const int yn = more ? m.y0 + (int)__builtin_ctzll(act) : y;
+    McPair nlo = hi, nhi = hi;
+    if (more) {
+      if (yn != y + 1) nlo = valid ? mc_load(m, nx, yn) : McPair{0, 0, 0, 0};
+      nhi = valid ? mc_load(m, nx, yn + 1) : McPair{0, 0, 0, 0};
+    }
+    const int cfg = valid ? (mc_nib(lo, iso) | (mc_nib(hi, iso) << 2)) : 0;
     const int n = valid ? tab.ntri[cfg] : 0;
     const McBits bits = mc_bits((unsigned)n);
     const unsigned pre = mc_prefix(bits), total = mc_total(bits);
@@ -313,15 +330,18 @@ __global__ __launch_bounds__(256) void mc_emit_kernel(
     }
     ncube += __popcll(has);
     ntask += (int)total;
-    if (ntask >= 64 || (y + 1 == m.y1 && ntask > 0)) {
+    if (ntask >= 64 || (!more && ntask > 0)) {
       __builtin_amdgcn_wave_barrier();
       mc_flush(q, ntask, tab, m, nx, ny, iso, tris, cube_id, max_tris);
       __builtin_amdgcn_wave_barrier();
       ncube = 0;
       ntask = 0;
     }
-    nlo = nhi;
-    hi = nxt;
+    if (!more) break;
+    act &= act - 1;
+    y = yn;
+    lo = nlo;
+    hi = nhi;
   }
 }
 
@@ -359,8 +379,8 @@ hipError_t launch_mc_emit(const float* vol, int nx, int ny, const McGrid& g, flo
                           const unsigned long long* tile_off, float* tris, long long* cube_id,
                           long long max_tris, hipStream_t s) {
   hipLaunchKernelGGL(mc_emit_kernel, dim3((unsigned)((g.nwaves + 3) / 4)), dim3(256), 0, s, vol,
-                     nx, ny, (int)g.nstrip, (int)g.nych, g.nwaves, iso, table, off_local,
-                     tile_off, tris, cube_id, max_tris);
+                     nx, ny, (int)g.nstrip, (int)g.nych, g.nwaves, g.ncnt, g.ntile, iso, table,
+                     off_local, tile_off, tris, cube_id, max_tris);
   return hipGetLastError();
 }
 
