@@ -166,3 +166,25 @@ def test_loso_full_size_vs_oracle():
     print(f"full: loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
     assert abs(L - L_o) <= 1e-9 * abs(L_o)
     np.testing.assert_allclose(g, g_o, rtol=1e-4)
+
+
+@pytest.mark.slow
+def test_loso_full_size_drift_with_masks_vs_oracle():
+    """The differentiation workload at full size with the slice predictor and
+    edge masks (10 % of the pixels) on every slice."""
+    import torch
+    import paper_2303_09523_amd as P
+    w = W.workload("loso_16x128")
+    s, _ = W.make_inputs(w)
+    e = (np.random.default_rng(21).random(s.shape) < 0.1).astype(np.uint8)
+    th = ("exponential", 0.1, 1.0, 2.0)
+    L_o, g_o = O.loso_loss_grad(s, w.radius, th, edges=e, drift="linear_z")
+    n, ny, nx = s.shape
+    plan = P.Plan(nx, ny, n, 2, w.radius, 4, drift="linear_z")
+    print("loso_16x128 drift with masks", flush=True)
+    L = float(plan.loso_forward(torch.from_numpy(s).cuda(), th, torch.from_numpy(e).cuda()).item())
+    g = plan.loso_backward().cpu().numpy()
+    plan.close()
+    print(f"full drift: loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
+    assert abs(L - L_o) <= 1e-9 * abs(L_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-4)
