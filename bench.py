@@ -96,21 +96,26 @@ TRAFFIC_SOURCES = ["okrig_internal.h", "solver_core.h", "solver_refine.h", "kern
                    "kernels_mixed.hip"]
 
 
-def kernel_source_hash() -> str:
+MESH_TRAFFIC_SOURCES = ["okrig_internal.h", "kernels_mcubes.hip"]
+
+
+def _source_hash(names) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in TRAFFIC_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2303_09523_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(args):
-    """HBM bytes of one step's solve launches from the committed counter
-    summary (profiles/traffic_<workload>_<precision>_r<refine_max>.txt), or
-    None when it is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles",
-                        f"traffic_{args.workload}_{args.precision}_r{args.refine_max}.txt")
+def kernel_source_hash() -> str:
+    return _source_hash(TRAFFIC_SOURCES)
+
+
+def _counter_summary(name, sources, key):
+    """A value of a committed counter summary under profiles/, or None when
+    the file is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -119,12 +124,26 @@ def traffic_from_profiles(args):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != _source_hash(sources):
         return None
     try:
-        return float(kv["solve_hbm_bytes_per_step"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def traffic_from_profiles(args):
+    """HBM bytes of one step's solve launches from the committed counter
+    summary (profiles/traffic_<workload>_<precision>_r<refine_max>.txt)."""
+    return _counter_summary(f"traffic_{args.workload}_{args.precision}_r{args.refine_max}.txt",
+                            TRAFFIC_SOURCES, "solve_hbm_bytes_per_step")
+
+
+def mesh_traffic_from_profiles(workload):
+    """HBM bytes of one marching-cubes call on the workload's volume
+    (profiles/traffic_mcubes_<workload>.txt)."""
+    return _counter_summary(f"traffic_mcubes_{workload}.txt", MESH_TRAFFIC_SOURCES,
+                            "mesh_hbm_bytes_per_call")
 
 
 def class_counts(bucket, nb):
@@ -360,7 +379,7 @@ def main():
                 "bound": "hbm", "achieved": round(mbytes / (mesh_ms * 1e-3) / 1e9, 2),
                 "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
                 "frac": round(mbytes / (mesh_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"], 5),
-                "traffic": None}}
+                "traffic": mesh_traffic_from_profiles(args.workload)}}
         del tris, ids
         print(f"# marching cubes: {mesh_ms:.3f} ms, {ntri} triangles", file=sys.stderr,
               flush=True)
