@@ -1,8 +1,8 @@
 """Leave-one-slice-out loss as a torch.autograd.Function.
 
 forward: okr_loso_forward (refined batched solves on the GPU) -> scalar loss.
-backward: okr_loso_backward (adjoint of the bordered kriging systems) ->
-dL/d(nugget, sill, range). Both run entirely in the HIP library; this module
+backward: okr_loso_backward (adjoint of the kriging systems of Appendix A,
+with the slice predictor on a drift plan) -> dL/d(nugget, sill, range). Both run entirely in the HIP library; this module
 only passes the variogram parameters and device pointers.
 """
 from __future__ import annotations
