@@ -204,7 +204,10 @@ okr_status okr_loso_forward(okr_plan* plan, const okr_variogram* vario, const fl
  * Appendix A, K = [[C, Q], [Q^T, 0]] (Q = 1, or [1 s] with the drift):
  * nu = K^{-1} [e z; 0], dL/dtheta = nu_w^T dc0/dtheta - nu_w^T dC/dtheta w
  * (Q does not depend on the variogram).
- * d_grad: device double[3]. OKR_E_INVALID_ARG if no forward preceded it. */
+ * d_grad: device double[3]. OKR_E_INVALID_ARG unless an okr_loso_forward
+ * preceded it with no okr_execute, okr_select, okr_plan_autotune or
+ * okr_krige_points on the plan in between (those overwrite the
+ * selection and counters the adjoint reads). */
 okr_status okr_loso_backward(okr_plan* plan, double* d_grad);
 
 /* Ordinary kriging of explicitly given point sets (Appendix A with the single

@@ -199,6 +199,7 @@ class Plan:
         v = _as_vario(vario)
         _lib.check(load().okr_loso_forward(self._h, C.byref(v), _ptr(slices), _ptr(edge),
                                            _ptr(loss)), self._h)
+        self.loso_token = getattr(self, "loso_token", 0) + 1
         return loss
 
     def loso_backward(self, grad=None):

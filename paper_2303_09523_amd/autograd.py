@@ -24,11 +24,15 @@ class LosoLoss(torch.autograd.Function):
         nug, sill, rng = (float(v) for v in theta.detach().cpu().tolist())
         loss = plan.loso_forward(slices, (model, nug, sill, rng), edge)
         ctx.plan = plan
+        ctx.token = plan.loso_token
         ctx.theta_device = theta.device
         return loss.clone()
 
     @staticmethod
     def backward(ctx, grad_out):
+        if ctx.plan.loso_token != ctx.token:
+            raise RuntimeError("LosoLoss.backward: the plan ran another leave-one-slice-out "
+                               "forward after this loss; its adjoint would belong to that one")
         g = ctx.plan.loso_backward()
         g = g.to(ctx.theta_device) * grad_out.to(ctx.theta_device)
         return g, None, None, None, None

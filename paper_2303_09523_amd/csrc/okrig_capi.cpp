@@ -590,6 +590,9 @@ okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const floa
   okr_status st = validate_vario(vario, &msg);
   if (st != OKR_OK) return fail(p, st, msg);
   if (!d_slices || !d_volume) return fail(p, OKR_E_INVALID_ARG, "slices and volume are required");
+  // the timed executes overwrite the selection, permutation and counters that
+  // a pending okr_loso_backward would read
+  p->loso_ready = false;
   if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL || p->geo.nslices < 2 || p->geo.f < 2) {
     p->tuned = true;
     return OKR_OK;
@@ -737,6 +740,7 @@ okr_status okr_select(okr_plan* p, const uint8_t* d_edge, uint64_t* d_bits, uint
   if (!p) return OKR_E_INVALID_ARG;
   if (!d_bits || !d_count) return fail(p, OKR_E_INVALID_ARG, "bits and count are required");
   const okr::Geometry& g = p->geo;
+  p->loso_ready = false;   // the counters a pending okr_loso_backward reads are reset
   if (g.nsys == 0) return OKR_OK;
   OKR_HIP(p, okr::launch_reset(p->ctr, p->stream));
   OKR_HIP(p, okr::launch_select(d_edge, g, p->rule, d_bits, d_count, p->ctr, p->stream));

@@ -133,6 +133,51 @@ def test_loso_backward_requires_forward():
     plan.close()
 
 
+@pytest.mark.parametrize("between", ["autotune", "select", "execute"])
+def test_loso_backward_refused_after_other_work(between):
+    """A call that rewrites the selection, permutation or counters between
+    the forward and the backward makes the backward an argument error (it
+    returns before any launch)."""
+    import torch
+    import paper_2303_09523_amd as P
+    s = _field(5, 12, 11)
+    st = torch.from_numpy(s).cuda()
+    plan = _plan(s)
+    th = ("exponential", 0.1, 1.0, 2.0)
+    plan.loso_forward(st, th)
+    if between == "autotune":
+        plan.autotune(st, th)
+    elif between == "select":
+        plan.select()
+    else:
+        plan.execute(st, th)
+    with pytest.raises(P.OkrError):
+        plan.loso_backward()
+    # a new forward makes the pair valid again
+    plan.loso_forward(st, th)
+    g = plan.loso_backward()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(g.cpu().numpy()))
+    plan.close()
+
+
+def test_loso_autograd_refuses_a_stale_forward():
+    import torch
+    from paper_2303_09523_amd.autograd import LosoLoss
+    s = _field(5, 12, 11)
+    st = torch.from_numpy(s).cuda()
+    plan = _plan(s)
+    t1 = torch.tensor([0.1, 1.0, 2.0], dtype=torch.float64, requires_grad=True)
+    t2 = torch.tensor([0.2, 1.0, 3.0], dtype=torch.float64, requires_grad=True)
+    l1 = LosoLoss.apply(t1, plan, st, None, "exponential")
+    l2 = LosoLoss.apply(t2, plan, st, None, "exponential")
+    with pytest.raises(RuntimeError):
+        l1.backward()
+    l2.backward()
+    assert torch.isfinite(t2.grad).all()
+    plan.close()
+
+
 def test_adam_trajectory_vs_oracle():
     import torch
     from paper_2303_09523_amd.autograd import fit_variogram
