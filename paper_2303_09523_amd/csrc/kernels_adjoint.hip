@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   __shared__ AdjSmem as;
   __shared__ WaveScratch<float> wsa[4];
   __shared__ MixedScratch msa[4];
+  __shared__ f32x4 xsa[4 * NB * 64];   // each wave's diagonal L^{-T} tiles
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
       double est = 0.0, zscale = 1.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      mixed_system<NB, 0, true, LosoSmem>(n, nb, ws, sm, mx, msm, ncand, 1, a.sill, 0.0, &est, &var, mn, mxp, bad,
+      mixed_system<NB, 0, true, LosoSmem>(n, nb, ws, sm, mx, xsa + 64 * NB * wid, msm, ncand, 1, a.sill, 0.0, &est, &var, mn, mxp, bad,
                           BACKWARD ? wv : nullptr, &zscale);
       est = __shfl(est, 0, 64);
       const unsigned gap = sys / plane;

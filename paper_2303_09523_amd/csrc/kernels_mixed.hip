@@ -43,13 +43,14 @@ template <bool CORR> constexpr int mixed_waves() { return CORR ? 4 : 8; }
 
 template <int NB, int UPD, bool CORR>
 __global__ __launch_bounds__(64 * mixed_waves<CORR>())
-__attribute__((amdgpu_waves_per_eu(CORR ? 1 : 4)))
+__attribute__((amdgpu_waves_per_eu(CORR ? 2 : 4)))
 void mixed_class_kernel(SolveArgs a) {
   constexpr int W = mixed_waves<CORR>();
   __shared__ Smem<float> sm;
   __shared__ MixedSmem msm;
   __shared__ WaveScratch<float> wsa[W];
   __shared__ MixedScratch msa[W];
+  __shared__ f32x4 xsa[CORR ? W * NB * 64 : 1];   // each wave's diagonal L^{-T} tiles
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
@@ -98,7 +99,7 @@ void mixed_class_kernel(SolveArgs a) {
       float var = 0.0f, mn, mxp;
       bool bad;
       double scale = 1.0;
-      const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, msm, ncand, ntgt, a.sill,
+      const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, xsa + 64 * NB * wid, msm, ncand, ntgt, a.sill,
                                                     a.refine_kappa, &est, &var, mn, mxp, bad,
                                                     nullptr, &scale);
       bool route = false;

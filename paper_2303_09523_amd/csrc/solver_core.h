@@ -97,6 +97,37 @@ struct WaveScratch {
 // classes and a zero at index 32, which columns that are not data points read.
 constexpr int kT0StrideF = kT0Stride + 1;
 
+// Covariance of two window points by their offset. The covariance depends only
+// on the offset of the two points (translation invariance), so one table over
+// every in-plane offset (-2R..2R per axis, R the largest radius), for each
+// pair of slices, replaces a table over candidate pairs: 676 entries instead
+// of 98 x 98. The entry of row point p and column point q sits at
+// conv_row(p) + conv_col(q), layout [s_p][s_q][dy + 2R][dx + 2R] with
+// (dy, dx) the offset of q from p.
+constexpr int kConvHalf = 2 * kMaxRadius;
+constexpr int kConvQ = 2 * kConvHalf + 1;
+constexpr int kConvSub = kConvQ * kConvQ;
+constexpr int kConvSize = 4 * kConvSub;
+
+// From a candidate descriptor (bits 8..15: (s<<6)|((dy+r)<<3)|(dx+r)).
+__device__ __forceinline__ int conv_row(int d) {
+  const int c = (d >> 8) & 0xff;
+  return (c >> 6) * (2 * kConvSub) + (kConvHalf - ((c >> 3) & 7)) * kConvQ + (kConvHalf - (c & 7));
+}
+__device__ __forceinline__ int conv_col(int d) {
+  const int c = (d >> 8) & 0xff;
+  return (c >> 6) * kConvSub + ((c >> 3) & 7) * kConvQ + (c & 7);
+}
+// Pair class ((ds<<6)|(|dy|<<3)|(|dx|)) of offset-table entry i.
+__device__ __forceinline__ int conv_class(int i) {
+  const int sr = i / (2 * kConvSub);
+  const int rem = i - sr * (2 * kConvSub);
+  const int sc = rem / kConvSub;
+  const int k = rem - sc * kConvSub;
+  const int dy = k / kConvQ - kConvHalf, dx = k % kConvQ - kConvHalf;
+  return ((sr ^ sc) << 6) | ((dy < 0 ? -dy : dy) << 3) | (dx < 0 ? -dx : dx);
+}
+
 // Per-workgroup tables (each kernel declares its waves' WaveScratch beside
 // them). Every covariance table holds NEGATED values (the factorisation works
 // on S = -M), so an assembled entry needs no sign flip.
@@ -116,7 +147,7 @@ template <> struct Smem<float> {
   float zr[128];             // zeros: the row read by padding rows and the value row
   int sdesc[128];
   int bz;
-  float cc[kMaxCand * kMaxCand];
+  float cc[kConvSize];       // -Cov by offset (conv_row / conv_col)
 };
 
 // Candidate descriptor: bits 0..6 candidate index; bits 8..15
@@ -173,9 +204,10 @@ constexpr int kOffZr = offsetof(Smem<float>, zr);
 constexpr int kOffCc = offsetof(Smem<float>, cc);
 constexpr int kTailOfs = (4 * kT0Stride) << 16;
 
-// Column offsets of a candidate descriptor (bits 0..6 candidate, 16..20 class).
+// Column offsets of a candidate descriptor: its offset-table column (bytes)
+// in the low half, its target-table class (bits 16..20, bytes) in the high half.
 __device__ __forceinline__ int f32_ofs(int d) {
-  return ((d & 0x7f) << 2) | (((d >> 16) & 31) << 18);
+  return (conv_col(d) << 2) | (((d >> 16) & 31) << 18);
 }
 
 __device__ __forceinline__ float lds_at(const Smem<float>& sm, int off) {
@@ -192,12 +224,12 @@ __device__ __forceinline__ void f32_rows(int n, int bstart, int bz, int ncand,
 #pragma unroll
   for (int i = 0; i < NB - 1; ++i) {   // data or padding (border rows are in the last block)
     const int p = 16 * i + r;
-    rb[i] = p < n ? kOffCc + (ws.ofs[p] & 0xffff) * ncand : kOffZr;
+    rb[i] = p < n ? kOffCc + 4 * conv_row(ws.desc[p]) : kOffZr;
   }
   const int p = 16 * (NB - 1) + r;
   const int b = p - bstart;
   int o;
-  if (p < n) o = kOffCc + (ws.ofs[p] & 0xffff) * ncand;
+  if (p < n) o = kOffCc + 4 * conv_row(ws.desc[p]);
   else if (b < 0 || b == bz) o = kOffZr;
   else if (b == 0) o = kOffBt;
   else if (b < bz) o = kOffBt + 4 * kT0StrideF;
@@ -713,12 +745,9 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
     __syncthreads();
   }
   if constexpr (sizeof(T) == 4) {
-    // (negated) covariance of every candidate pair, rounded once from the FP64 table
-    const int nc = a.geo.ncand;
-    for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
-      const int p = i / nc, q = i - p * nc;
-      sm.cc[i] = (float)(-(a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale));
-    }
+    // (negated) covariance of every offset, rounded once from the FP64 table
+    for (int i = threadIdx.x; i < kConvSize; i += blockDim.x)
+      sm.cc[i] = (float)(-(a.tab.tc_d[conv_class(i)] * tscale));
     __syncthreads();
   }
 }

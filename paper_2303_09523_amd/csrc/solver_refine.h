@@ -123,15 +123,16 @@ __device__ __forceinline__ f32x4 neg_transpose(const f32x4& x, float* buf) {
 }
 
 // Left-looking factorisation (FP32 diagonal / off-diagonal solves, UPD trailing
-// updates) keeping every L tile and every diagonal L^{-T} tile (Xs; the last
-// one only with LAST_X, for the back-substitution). Leaves the last diagonal
-// tile (with G in its border corner) in buf.
+// updates) keeping every L tile in registers. With LAST_X (the back-substitution
+// follows) every diagonal L^{-T} tile, the last one included, goes to the wave's
+// LDS area xs (tile j at xs[64 j + lane]). Leaves the last diagonal tile (with
+// G in its border corner) in buf.
 template <int NB, int UPD, bool LAST_X>
 __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<float>& ws,
                                             const Smem<float>& sm, int ncand, float* buf,
                                             float& minpiv, float& maxpiv, bool& bad,
                                             PairStore<UPD> (&Ls)[NB][(NB + 1) / 2],
-                                            f32x4 (&Xs)[NB]) {
+                                            f32x4* xs) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   constexpr int N = 16 * NB;
@@ -168,7 +169,7 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     f32x4 X;
     f32x4 D = S[j];
     diag_factor(D, X, ne, buf, minpiv, maxpiv, bad, j < NB - 1 || LAST_X);
-    Xs[j] = X;
+    if constexpr (LAST_X) xs[64 * j + lane] = X;
     if (j < NB - 1) {
       const f32x4 NI = neg_transpose(X, buf);
       // FP16 read-out: the off-diagonal solves as split products too (three
@@ -210,12 +211,12 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
 // 1 + t: C^{-1} c0_t); write_rows copies them to LDS.
 template <int NB, int UPD>
 __device__ __forceinline__ void back_substitute(int nb, const PairStore<UPD> (&Ls)[NB][(NB + 1) / 2],
-                                                const f32x4 (&Xs)[NB], float* buf, f32x4 (&Z)[NB]) {
+                                                const f32x4* xs, float* buf, f32x4 (&Z)[NB]) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int ne = 16 - nb;
   {
-    const f32x4 NI = neg_transpose(Xs[NB - 1], buf);
+    const f32x4 NI = neg_transpose(xs[64 * (NB - 1) + lane], buf);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Z[NB - 1][v] = (r >= ne && 4 * g + v < ne) ? NI[v] : 0.0f;
   }
@@ -231,7 +232,7 @@ __device__ __forceinline__ void back_substitute(int nb, const PairStore<UPD> (&L
       acc = acc_qpt(acc, Z[K], P);
     }
     const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    Z[I] = acc_qpt(z, acc, Xs[I]);
+    Z[I] = acc_qpt(z, acc, xs[64 * I + lane]);
   }
 }
 
@@ -315,14 +316,11 @@ struct MixedTables {
   double t064[kT0Size];
 };
 
-// Refined estimates: the FP64 covariance of every candidate pair, so an entry
-// of the FP64 matrix-vector product is one LDS read (the row stride is odd to
-// spread the lanes' rows over the banks).
-constexpr int kCcStride = kMaxCand | 1;
+// Refined estimates: the FP64 covariance of every point offset (layout of
+// conv_row / conv_col), so an entry of the FP64 matrix-vector product is one
+// LDS read.
 struct MixedSmem : MixedTables {
-  double cc64[kMaxCand * kCcStride];
-  __device__ __forceinline__ const double* row(int c) const { return cc64 + c * kCcStride; }
-  __device__ __forceinline__ double at(const double* row, int cq) const { return row[cq]; }
+  double cc64[kConvSize];
 };
 
 // Leave-one-slice-out blocks also need the pair class (for the derivative
@@ -341,14 +339,11 @@ __device__ __forceinline__ void mixed_tables(const SolveArgs& a, MixedTables& mt
 
 // Block set-up of the refined kernels (covariances times tscale). Needs the
 // block's candidate descriptors.
-__device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float>& sm, MixedSmem& msm,
+__device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float>&, MixedSmem& msm,
                                             double tscale) {
   mixed_tables(a, msm, tscale);
-  const int nc = a.geo.ncand;
-  for (int i = threadIdx.x; i < nc * nc; i += blockDim.x) {
-    const int p = i / nc, q = i - p * nc;
-    msm.cc64[p * kCcStride + q] = a.tab.tc_d[pair_class(sm.sdesc[p], sm.sdesc[q])] * tscale;
-  }
+  for (int i = threadIdx.x; i < kConvSize; i += blockDim.x)
+    msm.cc64[i] = a.tab.tc_d[conv_class(i)] * tscale;
 }
 __device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float>& sm, LosoSmem& msm,
                                             double tscale) {
@@ -364,6 +359,36 @@ __device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float
 // (C v)_p for the lane's points p = lane, lane + 64, in FP64. v is indexed by
 // candidate (zero for dropped candidates), so the loop runs over the whole
 // window with fixed offsets from each lane's row: no index loads on the way.
+// Offset table: the window's rows of candidates, (dy, dx) in order.
+__device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, const double* vc,
+                                         const MixedSmem& ms, double& out0, double& out1) {
+  const int lane = threadIdx.x & 63;
+  const double* row0 = ms.cc64 + conv_row(lane < n ? desc[lane] : 0);
+  const double* row1 = ms.cc64 + conv_row(lane + 64 < n ? desc[lane + 64] : 0);
+  // ncand = 2 W^2
+  int W = 1;
+  while (2 * W * W < ncand) ++W;
+  double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0};
+  int c = 0;
+  for (int s = 0; s < 2; ++s) {
+    for (int y = 0; y < W; ++y) {
+      const int k = s * kConvSub + y * kConvQ;
+#pragma unroll
+      for (int x = 0; x < kMaxWin; ++x) {
+        if (x < W) {
+          const double vq = vc[c + x];
+          a0[x & 3] += row0[k + x] * vq;
+          a1[x & 3] += row1[k + x] * vq;
+        }
+      }
+      c += W;
+    }
+  }
+  out0 = lane < n ? (a0[0] + a0[1]) + (a0[2] + a0[3]) : 0.0;
+  out1 = lane + 64 < n ? (a1[0] + a1[1]) + (a1[2] + a1[3]) : 0.0;
+}
+
+// The same over the class-indexed pair table of the leave-one-slice-out blocks.
 template <typename MS>
 __device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, const double* vc,
                                          const MS& ms, double& out0, double& out1) {
@@ -394,7 +419,7 @@ __device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, cons
 // is the factorisation's Schur read-out in the normalised units.
 template <int NB, int UPD, bool CORR, typename MS>
 __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& ws, const Smem<float>& sm,
-                                             MixedScratch& mx, const MS& ms, int ncand,
+                                             MixedScratch& mx, f32x4* xs, const MS& ms, int ncand,
                                              int ntgt, double sill, double refine_kappa,
                                              double* est_out, float* var_out, float& mn,
                                              float& mxp, bool& bad, double* w_out = nullptr,
@@ -419,11 +444,10 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   __builtin_amdgcn_wave_barrier();
   // ---- 2. factorisation ----
   PairStore<UPD> Ls[NB][(NB + 1) / 2];
-  f32x4 Xs[NB];
   mn = 3.0e38f;
   mxp = 0.0f;
   bad = false;
-  factor_keep<NB, UPD, CORR>(n, nb, ws, sm, ncand, ws.buf, mn, mxp, bad, Ls, Xs);
+  factor_keep<NB, UPD, CORR>(n, nb, ws, sm, ncand, ws.buf, mn, mxp, bad, Ls, xs);
   const int ne = 16 - nb;
   float est_r = 0.0f;
   if (lane < ntgt) {
@@ -441,7 +465,7 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' (x_s = C^{-1} s) ----
   // Slots of mx.x: 0 x_1, 1 x_z, 2.. the staged targets' x_t, kSlotXs x_s.
   f32x4 Z[NB];
-  back_substitute<NB, UPD>(nb, Ls, Xs, ws.buf, Z);
+  back_substitute<NB, UPD>(nb, Ls, xs, ws.buf, Z);
   const int dr = sm.bz - 1;   // 1 with the slice predictor (border rows 1, s, z, c0...)
   const int tcnt0 = ntgt < kRowTargets ? ntgt : kRowTargets;
   if (!dr) {
