@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   __shared__ AdjSmem as;
   __shared__ WaveScratch<float> wsa[4];
   __shared__ MixedScratch msa[4];
-  __shared__ f32x4 xsa[4 * NB * 64];   // each wave's diagonal L^{-T} tiles
+  __shared__ f32x4 xsa[4 * area_vec4<NB>()];   // each wave's area (see area_vec4)
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
       double est = 0.0, zscale = 1.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      mixed_system<NB, 0, true, LosoSmem>(n, nb, ws, sm, mx, xsa + 64 * NB * wid, msm, ncand, 1, a.sill, 0.0, &est, &var, mn, mxp, bad,
+      mixed_system<NB, 0, true, LosoSmem>(n, nb, ws, sm, mx, xsa + area_vec4<NB>() * wid, msm, ncand, 1, a.sill, 0.0, &est, &var, mn, mxp, bad,
                           BACKWARD ? wv : nullptr, &zscale);
       est = __shfl(est, 0, 64);
       const unsigned gap = sys / plane;
@@ -98,8 +98,8 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
         const double fac = e * zscale / a.sill;
         const int p0 = lane, p1 = lane + 64;
         const int e0 = p0 < n ? ws.desc[p0] : 0, e1 = p1 < n ? ws.desc[p1] : 0;
-        const double nu0 = p0 < n ? fac * mx.nuc[e0 & 0x7f] : 0.0;
-        const double nu1 = p1 < n ? fac * mx.nuc[e1 & 0x7f] : 0.0;
+        const double nu0 = p0 < n ? fac * area_nuc(xsa + area_vec4<NB>() * wid)[e0 & 0x7f] : 0.0;
+        const double nu1 = p1 < n ? fac * area_nuc(xsa + area_vec4<NB>() * wid)[e1 & 0x7f] : 0.0;
         const uint8_t* row0 = msm.row(e0 & 0x7f);
         const uint8_t* row1 = msm.row(e1 & 0x7f);
         double dcw0[3] = {0, 0, 0}, dcw1[3] = {0, 0, 0};

@@ -50,7 +50,7 @@ void mixed_class_kernel(SolveArgs a) {
   __shared__ MixedSmem msm;
   __shared__ WaveScratch<float> wsa[W];
   __shared__ MixedScratch msa[W];
-  __shared__ f32x4 xsa[CORR ? W * NB * 64 : 1];   // each wave's diagonal L^{-T} tiles
+  __shared__ f32x4 xsa[CORR ? W * area_vec4<NB>() : 1];   // each wave's area (see area_vec4)
   const double tscale = 1.0 / a.sill;
   block_setup<float>(a, sm, tscale);
   mixed_setup(a, sm, msm, tscale);
@@ -99,7 +99,7 @@ void mixed_class_kernel(SolveArgs a) {
       float var = 0.0f, mn, mxp;
       bool bad;
       double scale = 1.0;
-      const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, xsa + 64 * NB * wid, msm, ncand, ntgt, a.sill,
+      const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, xsa + area_vec4<NB>() * wid, msm, ncand, ntgt, a.sill,
                                                     a.refine_kappa, &est, &var, mn, mxp, bad,
                                                     nullptr, &scale);
       bool route = false;

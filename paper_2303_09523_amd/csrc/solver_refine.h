@@ -172,11 +172,10 @@ __device__ __forceinline__ void factor_keep(int n, int nb, const WaveScratch<flo
     if constexpr (LAST_X) xs[64 * j + lane] = X;
     if (j < NB - 1) {
       const f32x4 NI = neg_transpose(X, buf);
-      // FP16 read-out: the off-diagonal solves as split products too (three
+      // FP16 halves: the off-diagonal solves as split products too (three
       // 16-cycle MFMAs instead of four 32-cycle FP32 ones). Kept in FP32 for
-      // BF16 halves (too few bits for the explicit inverse) and for the
-      // corrected form, whose result is second order in the factor's error.
-      if constexpr (UPD != 1 || LAST_X) {
+      // BF16 halves (too few bits for the explicit inverse).
+      if constexpr (UPD != 1) {
 #pragma unroll
         for (int i = j + 1; i < NB; ++i) {
           const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -286,6 +285,21 @@ __device__ __forceinline__ void wave_sums(double (&x)[K]) {
     x[k] = (lane_value(x[k], 0) + lane_value(x[k], 16)) + (lane_value(x[k], 32) + lane_value(x[k], 48));
 }
 
+template <int K>
+__device__ __forceinline__ void wave_sums_f(float (&x)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_f<0xB1>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_f<0x4E>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_f<0x124>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_f<0x128>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    x[k] = (lane_value(x[k], 0) + lane_value(x[k], 16)) + (lane_value(x[k], 32) + lane_value(x[k], 48));
+}
+
 __device__ __forceinline__ double wave_sum_d(double x) {
   double s[1] = {x};
   wave_sums(s);
@@ -304,11 +318,24 @@ __device__ __forceinline__ float wave_max_abs(float x) {
 // One system with the FP64-corrected estimate (see kernels_mixed.hip).
 constexpr int kRowTargets = 3;   // targets whose solution rows are staged at once
 constexpr int kSlotXs = 2 + kRowTargets;
+constexpr int kXRows = 3 + kRowTargets;
 struct MixedScratch {
-  float x[3 + kRowTargets][128];   // x_1, x_z, x_t of up to kRowTargets targets, x_s
   float zr[128];                   // raw data values
-  double nuc[128];                 // nu_w by candidate index (0 for dropped candidates)
 };
+// Each wave's LDS area holds the diagonal L^{-T} tiles (64 f32x4 per block)
+// during the factorisation and the back-substitution, and afterwards, in the
+// same bytes, the solution rows x[kXRows][128] (x_1, x_z, x_t of up to
+// kRowTargets targets, x_s) and nu_w by candidate index (double[128], 0 for
+// dropped candidates).
+template <int NB> constexpr int area_vec4() {
+  return NB * 64 > (kXRows * 128 * 4 + 128 * 8) / 16 ? NB * 64 : (kXRows * 128 * 4 + 128 * 8) / 16;
+}
+__device__ __forceinline__ float (*area_x(f32x4* area))[128] {
+  return reinterpret_cast<float (*)[128]>(area);
+}
+__device__ __forceinline__ double* area_nuc(f32x4* area) {
+  return reinterpret_cast<double*>(reinterpret_cast<float*>(area) + kXRows * 128);
+}
 
 // FP64 tables shared by the refined kernels' blocks.
 struct MixedTables {
@@ -463,29 +490,37 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
     return false;
   }
   // ---- 3. explicit solutions x_1 = C^{-1} 1, x_z = C^{-1} z' (x_s = C^{-1} s) ----
-  // Slots of mx.x: 0 x_1, 1 x_z, 2.. the staged targets' x_t, kSlotXs x_s.
+  // Slots of x: 0 x_1, 1 x_z, 2.. the staged targets' x_t, kSlotXs x_s (in the area
+  // of the diagonal tiles, which the back-substitution has finished reading).
+  float (*const xrow)[128] = area_x(xs);
+  double* const nuc = area_nuc(xs);
+  __builtin_amdgcn_wave_barrier();
   f32x4 Z[NB];
   back_substitute<NB, UPD>(nb, Ls, xs, ws.buf, Z);
   const int dr = sm.bz - 1;   // 1 with the slice predictor (border rows 1, s, z, c0...)
   const int tcnt0 = ntgt < kRowTargets ? ntgt : kRowTargets;
   if (!dr) {
-    write_rows<NB>(Z, ne, 2 + tcnt0, 0, mx.x);
+    write_rows<NB>(Z, ne, 2 + tcnt0, 0, xrow);
   } else {
-    write_rows<NB>(Z, ne, 1, 0, mx.x);
-    write_rows<NB>(Z, ne + 1, 1, kSlotXs, mx.x);
-    write_rows<NB>(Z, ne + 2, 1 + tcnt0, 1, mx.x);
+    write_rows<NB>(Z, ne, 1, 0, xrow);
+    write_rows<NB>(Z, ne + 1, 1, kSlotXs, xrow);
+    write_rows<NB>(Z, ne + 2, 1 + tcnt0, 1, xrow);
   }
-  const double x1_0 = p0 < n ? (double)mx.x[0][p0] : 0.0, x1_1 = p1 < n ? (double)mx.x[0][p1] : 0.0;
-  const double xz_0 = p0 < n ? (double)mx.x[1][p0] : 0.0, xz_1 = p1 < n ? (double)mx.x[1][p1] : 0.0;
-  const double xs_0 = (dr && p0 < n) ? (double)mx.x[kSlotXs][p0] : 0.0;
-  const double xs_1 = (dr && p1 < n) ? (double)mx.x[kSlotXs][p1] : 0.0;
+  const double x1_0 = p0 < n ? (double)xrow[0][p0] : 0.0, x1_1 = p1 < n ? (double)xrow[0][p1] : 0.0;
+  const double xz_0 = p0 < n ? (double)xrow[1][p0] : 0.0, xz_1 = p1 < n ? (double)xrow[1][p1] : 0.0;
+  const double xs_0 = (dr && p0 < n) ? (double)xrow[kSlotXs][p0] : 0.0;
+  const double xs_1 = (dr && p1 < n) ? (double)xrow[kSlotXs][p1] : 0.0;
   const double sl_0 = (dr && p0 < n) ? (double)((ws.desc[p0] >> 14) & 1) : 0.0;
   const double sl_1 = (dr && p1 < n) ? (double)((ws.desc[p1] >> 14) & 1) : 0.0;
   // multipliers of the adjoint system: OK nu_mu = 1'x_z / 1'x_1; with the
-  // slice predictor G (nu_1, nu_s) = (1'x_z, s'x_z), G = Q'C^-1 Q
-  double g[5] = {x1_0 + x1_1, xz_0 + xz_1, xs_0 + xs_1, sl_0 * xs_0 + sl_1 * xs_1,
-                 sl_0 * xz_0 + sl_1 * xz_1};
-  wave_sums(g);
+  // slice predictor G (nu_1, nu_s) = (1'x_z, s'x_z), G = Q'C^-1 Q. These and
+  // the multipliers of the targets below are sums of FP32 solution entries,
+  // summed in FP32: the corrected estimate is exact for any approximate nu
+  // (the residual absorbs it) and second order in the weights' error.
+  float gf[5] = {(float)x1_0 + (float)x1_1, (float)xz_0 + (float)xz_1, (float)xs_0 + (float)xs_1,
+                 (float)(sl_0 * xs_0) + (float)(sl_1 * xs_1), (float)(sl_0 * xz_0) + (float)(sl_1 * xz_1)};
+  wave_sums_f(gf);
+  const double g[5] = {(double)gf[0], (double)gf[1], (double)gf[2], (double)gf[3], (double)gf[4]};
   const double g11 = g[0], g1s = g[2], gss = g[3];
   const double det = g11 * gss - g1s * g1s;
   double nu_1, nu_s = 0.0;
@@ -496,11 +531,11 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
     nu_s = (g11 * g[4] - g1s * g[1]) / det;
   }
   const double nu0 = xz_0 - nu_1 * x1_0 - nu_s * xs_0, nu1 = xz_1 - nu_1 * x1_1 - nu_s * xs_1;
-  mx.nuc[lane] = 0.0;
-  mx.nuc[lane + 64] = 0.0;
+  nuc[lane] = 0.0;
+  nuc[lane + 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
-  if (p0 < n) mx.nuc[ws.desc[p0] & 0x7f] = nu0;
-  if (p1 < n) mx.nuc[ws.desc[p1] & 0x7f] = nu1;
+  if (p0 < n) nuc[ws.desc[p0] & 0x7f] = nu0;
+  if (p1 < n) nuc[ws.desc[p1] & 0x7f] = nu1;
   __builtin_amdgcn_wave_barrier();
   // ---- 4. FP64 correction ----
   // With h = z' - C nu_w - Q nu_phi (the FP64 residual of the adjoint system)
@@ -508,7 +543,7 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   //   A_t - phi_t'B + nu_phi'q0_t,  A_t = h'x_t + nu_w'c0_t,  B = x_Q'h + Q'nu_w
   // (OK: Q = 1, phi_t = mu_t; with the slice predictor Q = [1 s], q0_t = (1, t/f)).
   double cn0, cn1;
-  matvec64(n, ncand, ws.desc, mx.nuc, ms, cn0, cn1);
+  matvec64(n, ncand, ws.desc, nuc, ms, cn0, cn1);
   const double zd = (double)zref;
   const double sd = ldexp(1.0, ex);
   const double isd = ldexp(1.0, -ex);
@@ -518,31 +553,42 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   double B1 = 0.0, Bs = 0.0;
   for (int t0 = 1; t0 <= ntgt; t0 += kRowTargets) {
     const int cnt = (ntgt - t0 + 1) < kRowTargets ? (ntgt - t0 + 1) : kRowTargets;
-    if (t0 > 1) write_rows<NB>(Z, ne + sm.bz + t0, cnt, 2, mx.x);
-    double s[3 * kRowTargets + 2];
+    if (t0 > 1) write_rows<NB>(Z, ne + sm.bz + t0, cnt, 2, xrow);
+    // sf: 1'x_t, s'x_t (FP32); sv: A_t, then B (FP64)
+    float sf[2 * kRowTargets];
+    double sv[kRowTargets + 2];
 #pragma unroll
     for (int k = 0; k < kRowTargets; ++k) {
-      s[3 * k] = 0.0;
-      s[3 * k + 1] = 0.0;
-      s[3 * k + 2] = 0.0;
+      sf[2 * k] = 0.0f;
+      sf[2 * k + 1] = 0.0f;
+      sv[k] = 0.0;
       if (k < cnt) {
         const int t = t0 + k;
-        const double xt0 = p0 < n ? (double)mx.x[2 + k][p0] : 0.0;
-        const double xt1 = p1 < n ? (double)mx.x[2 + k][p1] : 0.0;
+        const float xf0 = p0 < n ? xrow[2 + k][p0] : 0.0f;
+        const float xf1 = p1 < n ? xrow[2 + k][p1] : 0.0f;
+        const double xt0 = (double)xf0, xt1 = (double)xf1;
         const double c00 = p0 < n ? ms.t064[(t - 1) * kT0Stride + (d0 >> 16)] : 0.0;
         const double c01 = p1 < n ? ms.t064[(t - 1) * kT0Stride + (d1 >> 16)] : 0.0;
-        s[3 * k] = xt0 + xt1;
-        s[3 * k + 1] = (h0 * xt0 + h1 * xt1) + (nu0 * c00 + nu1 * c01);
-        s[3 * k + 2] = sl_0 * xt0 + sl_1 * xt1;
+        sf[2 * k] = xf0 + xf1;
+        sv[k] = (h0 * xt0 + h1 * xt1) + (nu0 * c00 + nu1 * c01);
+        sf[2 * k + 1] = (float)sl_0 * xf0 + (float)sl_1 * xf1;
       }
     }
-    s[3 * kRowTargets] = t0 == 1 ? (h0 * x1_0 + h1 * x1_1) + (nu0 + nu1) : 0.0;
-    s[3 * kRowTargets + 1] = (t0 == 1 && dr) ? (h0 * xs_0 + h1 * xs_1) + (sl_0 * nu0 + sl_1 * nu1)
-                                             : 0.0;
-    wave_sums(s);
+    sv[kRowTargets] = t0 == 1 ? (h0 * x1_0 + h1 * x1_1) + (nu0 + nu1) : 0.0;
+    sv[kRowTargets + 1] = (t0 == 1 && dr) ? (h0 * xs_0 + h1 * xs_1) + (sl_0 * nu0 + sl_1 * nu1)
+                                          : 0.0;
+    wave_sums_f(sf);
+    wave_sums(sv);
+    double s[3 * kRowTargets];
+#pragma unroll
+    for (int k = 0; k < kRowTargets; ++k) {
+      s[3 * k] = (double)sf[2 * k];
+      s[3 * k + 1] = sv[k];
+      s[3 * k + 2] = (double)sf[2 * k + 1];
+    }
     if (t0 == 1) {
-      B1 = s[3 * kRowTargets];
-      Bs = s[3 * kRowTargets + 1];
+      B1 = sv[kRowTargets];
+      Bs = sv[kRowTargets + 1];
     }
 #pragma unroll
     for (int k = 0; k < kRowTargets; ++k) {
@@ -561,8 +607,8 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
         }
         if (lane == t - 1) *est_out = zd + sd * corr;
         if (w_out && t == 1) {
-          if (p0 < n) w_out[p0] = (double)mx.x[2][p0] - p1c * x1_0 - psc * xs_0;
-          if (p1 < n) w_out[p1] = (double)mx.x[2][p1] - p1c * x1_1 - psc * xs_1;
+          if (p0 < n) w_out[p0] = (double)xrow[2][p0] - p1c * x1_0 - psc * xs_0;
+          if (p1 < n) w_out[p1] = (double)xrow[2][p1] - p1c * x1_1 - psc * xs_1;
         }
       }
     }
