@@ -70,9 +70,9 @@ typedef enum { OKR_SPHERICAL = 0, OKR_EXPONENTIAL = 1, OKR_GAUSSIAN = 2 } okr_mo
 
 /* Arithmetic of the factorisation. Assembly and read-out are FP32 except in
  * OKR_FP64. MIXED_* use split low-precision MFMA products (hi + lo parts) with
- * FP32 accumulation, an FP64-residual correction for systems whose condition
- * estimate is large, and an FP64 re-solve of systems whose pivots flag
- * instability. */
+ * FP32 accumulation, optionally an FP64-residual correction of every system's
+ * estimate (refine_max = 1), and an FP64 re-solve of systems whose pivots flag
+ * instability or whose error bound exceeds refine_tol. */
 typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 3 } okr_precision;
 
 /* BATCHED: selection, size bucketing and one persistent factorisation launch,
@@ -102,22 +102,39 @@ typedef struct {
   int32_t min_points;   /* neighbour floor, 1..2*(2r+1)^2; 4 is the usual value */
   int32_t precision;    /* okr_precision */
   int32_t algo;         /* okr_algo */
-  double  refine_tol;   /* >= 0. With kappa the system's pivot-ratio condition
-                           estimate and u = 2^-24:
-                           MIXED_* with refine_max >= 1 run the FP64 correction
-                           on systems with kappa*u > refine_tol (0: on every
-                           system);
-                           MIXED_* with refine_max = 0 re-solve in FP64 the
-                           systems whose error indicator
-                           kappa*u*s / max(|z_hat|, 0.01*max|known voxel|)
+  double  refine_tol;   /* >= 0: per-voxel tolerance on the relative error
+                           |z_hat - z*| / max(|z*|, 0.01*max|known voxel|) (0 = no
+                           check). Precision control uses kappa_w, the 2-norm
+                           condition number of the covariance matrix of the whole
+                           window, computed on the host in FP64 for each new
+                           variogram; every system's covariance matrix is a
+                           principal submatrix of it, so no system is worse
+                           conditioned (eigenvalue interlacing). With u the unit
+                           roundoff of the factorisation (2^-24 FP32, 2^-22 split
+                           FP16, 2^-16 split BF16):
+                           FP32: kappa_w * 2^-24 > refine_tol sends every system
+                           to the FP64 re-solve;
+                           MIXED_* with refine_max = 0: a system whose indicator
+                           kappa_w*u*s / max(|z_hat|, 0.01*max|known voxel|)
                            exceeds refine_tol for some target (s: the power of
-                           two above the spread of the system's data; 0: none);
-                           FP32 re-solves systems with kappa*u > refine_tol in
-                           FP64 (0: never). Ignored by FP64. */
-  int32_t refine_max;   /* MIXED_*, 0..4: 0 = no correction (the low-precision
-                           factorisation's own read-out); >= 1 = the correction,
-                           taken once (it squares the relative error of the
-                           factorisation, so one step reaches the FP64 result) */
+                           two above the spread of its data) is re-solved in FP64;
+                           MIXED_* with refine_max = 1: every system takes the
+                           FP64-residual correction, which is exact up to
+                           (lambda - lambda~)'h (lambda~ = computed weights and
+                           multipliers, h = FP64 residual of the dual system);
+                           with the weights' relative error taken as
+                           min(1, 10*kappa_w*u), a system whose resulting bound
+                           min(1, 10*kappa_w*u) * (|w_t| |h_w| + |phi_t| |Q'nu_w|)
+                           exceeds refine_tol * max(|z_hat|, 0.01*max|known voxel|)
+                           for some target is unconverged: re-solved in FP64,
+                           flagged (bit 32) and counted (n_refine_unconverged).
+                           Ignored by FP64. Systems with a non-positive pivot are
+                           always re-solved in FP64. */
+  int32_t refine_max;   /* MIXED_*: 0 = no correction (the low-precision
+                           factorisation's own read-out); 1 = the FP64-residual
+                           correction, taken once (it squares the factorisation's
+                           relative error; what it cannot reach is re-solved in
+                           FP64, see refine_tol). Other values: OKR_E_INVALID_ARG. */
   int32_t strict;       /* 1: OKR_E_NOT_CONVERGED is returned at the next sync if a
                            system met a non-positive pivot in its FP64 re-solve */
   int32_t drift;        /* 0: ordinary kriging (Appendix A with the constant
@@ -148,6 +165,11 @@ typedef struct {
                                  8 full-window pattern weights + application, 9 unused */
   int64_t phase_calls[10];    /* launches timed per phase */
   int64_t n_not_converged;    /* systems whose FP64 re-solve also met a non-positive pivot */
+  int64_t n_refine_unconverged; /* systems whose correction left refine_tol unmet (each
+                                   re-solved in FP64, so also in n_fp64_fallback) */
+  double  kappa_window;       /* condition number of the full-window covariance matrix
+                                 used by the last execute's precision control (0 if
+                                 refine_tol was 0) */
 } okr_stats;
 
 #define OKR_PHASE_PLACE 0
@@ -176,7 +198,8 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
  *   d_flags    uint8 [(nslices-1)][ny][nx] per (column, gap) system; NULL =
  *              not written. Bits: 1 floor-filled, 2 FP64-residual correction,
  *              4 FP64 re-solve, 8 non-positive pivot in the first pass,
- *              16 non-positive pivot in the FP64 re-solve as well.
+ *              16 non-positive pivot in the FP64 re-solve as well,
+ *              32 correction did not reach refine_tol (re-solved in FP64).
  * Input and output buffers must not overlap. */
 okr_status okr_execute(okr_plan* plan, const okr_variogram* vario,
                        const float* d_slices, const uint8_t* d_edge,

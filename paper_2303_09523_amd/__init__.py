@@ -217,6 +217,7 @@ class Plan:
                 "n_fp64_fallback": s.n_fp64_fallback,
                 "n_nonpositive_pivot": s.n_nonpositive_pivot, "max_kappa_est": s.max_kappa_est,
                 "n_not_converged": s.n_not_converged,
+                "n_refine_unconverged": s.n_refine_unconverged, "kappa_window": s.kappa_window,
                 "phase_ms": dict(zip(_lib.PHASES, list(s.phase_ms))),
                 "phase_calls": dict(zip(_lib.PHASES, list(s.phase_calls)))}
 

@@ -45,7 +45,8 @@ class Stats(C.Structure):
                 ("n_floor_filled", C.c_int64), ("n_refined", C.c_int64),
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
                 ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 10),
-                ("phase_calls", C.c_int64 * 10), ("n_not_converged", C.c_int64)]
+                ("phase_calls", C.c_int64 * 10), ("n_not_converged", C.c_int64),
+                ("n_refine_unconverged", C.c_int64), ("kappa_window", C.c_double)]
 
 
 class OkrError(RuntimeError):

@@ -31,8 +31,6 @@
 namespace okr {
 namespace {
 
-constexpr double kUnitRoundoff32 = 5.9604644775390625e-8;   // 2^-24
-
 // Without the correction the kernel holds only the factorisation's live tiles;
 // it runs eight waves per workgroup, which share one copy of the block tables,
 // so that two workgroups fit a CU's LDS and each SIMD holds four waves (128
@@ -98,21 +96,37 @@ void mixed_class_kernel(SolveArgs a) {
       double est = 0.0;
       float var = 0.0f, mn, mxp;
       bool bad;
-      double scale = 1.0;
+      double scale = 1.0, readout = 0.0, bound = 0.0;
+      const bool check = CORR && a.refine_tol > 0.0;
       const bool corr = mixed_system<NB, UPD, CORR>(n, nbs, ws, sm, mx, xsa + area_vec4<NB>() * wid, msm, ncand, ntgt, a.sill,
                                                     a.refine_kappa, &est, &var, mn, mxp, bad,
-                                                    nullptr, &scale);
+                                                    nullptr, &scale, &readout,
+                                                    check ? &bound : nullptr);
       bool route = false;
+      uint8_t extra = 0;
       if (!CORR && a.route_tol > 0.0) {
-        // error indicator of the read-out per target: kappa u s / max(|z_hat|, 0.01 Zmax)
-        // (kappa: pivot-ratio estimate, s: the power of two bounding the data spread)
+        // error indicator of the read-out per target: kappa_w u s / max(|z_hat|, 0.01 Zmax)
+        // (kappa_w bounds the system's condition number, u is the factorisation's
+        // unit roundoff, s the power of two bounding the data spread)
         const double den = fmax(fabs(est), zfloor);
-        const double ind = (lane < ntgt && den > 0.0)
-                               ? ((double)mxp / (double)mn) * kUnitRoundoff32 * scale / den
-                               : 0.0;
+        const double ind = (lane < ntgt && den > 0.0) ? a.route_scale * scale / den : 0.0;
         route = __any(ind > a.route_tol);
       }
-      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally, route);
+      if (check && corr) {
+        // convergence: the error the correction leaves is at most the weights'
+        // relative error (rho_hat, from kappa_w and the factorisation's unit
+        // roundoff) times the bound mixed_system reports; the move of the
+        // estimate from the read-out, scaled the same way, is included as well
+        const double den = fmax(fabs(est), zfloor);
+        const double c = (lane < ntgt && den > 0.0)
+                             ? a.rho_hat * fmax(bound, fabs(est - readout)) / den : 0.0;
+        if (__any(c > a.refine_tol)) {
+          route = true;
+          extra = kFlagUnconverged;
+          tally.unconv += 1;
+        }
+      }
+      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally, route, extra);
       if (lane == 0 && a.flags && corr && !bad) a.flags[sys] |= kFlagRefined;
       refined += (corr && !bad) ? 1 : 0;
     }

@@ -61,6 +61,7 @@ __global__ void reset_kernel(DevCounters* c) {
     c->next2 = 0;
     c->floor_filled = 0;
     c->refined = 0;
+    c->unconverged = 0;
     c->fp64_fallback = 0;
     c->bad_pivot = 0;
     c->failed = 0;

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <tuple>
@@ -51,6 +52,12 @@ struct okr_plan {
   long long last_nsys = 0, last_kriged = 0;
   bool profiling = false;
   bool timers_off = false;      // no profiling marks while a graph is captured
+  // 2-norm condition number of the full-window covariance matrix for the last
+  // variogram it was computed for (every system's covariance matrix is a
+  // principal submatrix of it, so bounds their condition numbers)
+  bool kw_valid = false;
+  okr_variogram kw_vario{};
+  double kappa_w = 0.0;
   int grid_per_cu = 3;          // persistent workgroups per compute unit (autotuned)
   int upd = -1;                 // mixed trailing-update arithmetic (-1: from the precision)
   bool tuned = false;
@@ -169,8 +176,10 @@ okr_status validate_problem(const okr_problem* p, std::string* msg) {
     *msg = "with the slice predictor upsample must be in 1..14";
     return OKR_E_SHAPE;
   }
-  if (!(p->refine_tol >= 0.0) || p->refine_max < 0 || p->refine_max > 4) {
-    *msg = "refine_tol must be >= 0 and refine_max in 0..4";
+  if (!(p->refine_tol >= 0.0) || p->refine_max < 0 || p->refine_max > 1) {
+    *msg = "refine_tol must be >= 0 and refine_max 0 or 1 (one FP64-residual correction "
+           "squares the factorisation's relative error; systems it leaves above refine_tol "
+           "are re-solved in FP64)";
     return OKR_E_INVALID_ARG;
   }
   const long long plane = (long long)p->nx * p->ny;
@@ -276,6 +285,10 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.refine_kappa = 0.0;
   a.refine = 0;
   a.route_tol = 0.0;
+  a.route_scale = 0.0;
+  a.refine_tol = 0.0;
+  a.rho_hat = 1.0;
+  a.kappa_w = 0.0;
   a.upd = 1;
   a.nmax = okr::kHist - 1;
   a.fallback = nullptr;
@@ -431,6 +444,92 @@ bool force_fallback() {
   return force && force[0] == '1';
 }
 
+// Covariance of lag h (GSLIB convention, the library's variogram models).
+double host_cov(const okr_variogram& v, double h) {
+  if (h == 0.0) return v.sill;
+  const double q = h / v.range;
+  double rho;
+  if (v.model == OKR_SPHERICAL) rho = q < 1.0 ? 1.0 - 1.5 * q + 0.5 * q * q * q : 0.0;
+  else if (v.model == OKR_EXPONENTIAL) rho = std::exp(-3.0 * q);
+  else rho = std::exp(-3.0 * q * q);
+  return (v.sill - v.nugget) * rho;
+}
+
+// Smallest and largest eigenvalue of a symmetric matrix (cyclic Jacobi
+// rotations in FP64; a is overwritten).
+void sym_eig_range(std::vector<double>& a, int n, double* lmin, double* lmax) {
+  double fro = 0.0;
+  for (double x : a) fro += x * x;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += a[i * n + j] * a[i * n + j];
+    if (off <= 1e-32 * fro) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p * n + q];
+        if (std::fabs(apq) <= 1e-300) continue;
+        const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - sn * akq;
+          a[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - sn * aqk;
+          a[q * n + k] = sn * apk + c * aqk;
+        }
+      }
+    }
+  }
+  double mn = a[0], mx = a[0];
+  for (int i = 1; i < n; ++i) {
+    mn = std::min(mn, a[i * n + i]);
+    mx = std::max(mx, a[i * n + i]);
+  }
+  *lmin = mn;
+  *lmax = mx;
+}
+
+// Condition number of the covariance matrix of the whole (2r+1)^2 x 2 window
+// (known slices f apart). By eigenvalue interlacing no system's matrix, a
+// principal submatrix, is worse conditioned. Cached per variogram.
+double window_kappa(okr_plan* p, const okr_variogram& v) {
+  if (p->kw_valid && p->kw_vario.model == v.model && p->kw_vario.nugget == v.nugget &&
+      p->kw_vario.sill == v.sill && p->kw_vario.range == v.range)
+    return p->kappa_w;
+  const okr::Geometry& g = p->geo;
+  const int n = g.ncand;
+  std::vector<double> pts(3 * n), a((size_t)n * n);
+  for (int c = 0; c < n; ++c) {
+    const int sl = c / g.W2, o = c % g.W2;
+    pts[3 * c] = o % g.W - g.r;
+    pts[3 * c + 1] = o / g.W - g.r;
+    pts[3 * c + 2] = (double)sl * g.f;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double dx = pts[3 * i] - pts[3 * j], dy = pts[3 * i + 1] - pts[3 * j + 1],
+                   dz = pts[3 * i + 2] - pts[3 * j + 2];
+      a[(size_t)i * n + j] = host_cov(v, std::sqrt(dx * dx + dy * dy + dz * dz));
+    }
+  double lmin = 0.0, lmax = 0.0;
+  sym_eig_range(a, n, &lmin, &lmax);
+  p->kappa_w = lmin > 0.0 ? lmax / lmin : std::numeric_limits<double>::infinity();
+  p->kw_vario = v;
+  p->kw_valid = true;
+  return p->kappa_w;
+}
+
+// Unit roundoff of the factorisation arithmetic: FP32 updates, split FP16
+// products (hi + lo halves carry about 22 bits), split BF16 products (16 bits).
+double factor_roundoff(int upd) {
+  return upd == 2 ? std::ldexp(1.0, -16) : (upd == 1 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -24));
+}
+
 // The launch sequence of okr_execute on stream `strm` (the plan's stream, or
 // the capture stream of its graph).
 okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* vario,
@@ -475,20 +574,36 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
     a.nmax = g.ncand - 1;
   }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
-  // condition estimate x FP32 unit roundoff above refine_tol: FP32 systems go
-  // to the FP64 re-solve, mixed systems take the FP64 correction; without the
-  // correction, mixed systems whose error indicator exceeds refine_tol go to
-  // the FP64 re-solve
-  const double kappa_tol = p->prob.refine_tol / kUnitRoundoff32;
+  // Precision control against refine_tol (per-voxel relative error), with the
+  // window's condition number kappa_w bounding every system's:
+  //   FP32: kappa_w 2^-24 above refine_tol sends every system to FP64;
+  //   mixed read-out: per system, the indicator kappa_w u s / max(|z_hat|,
+  //     0.01 Zmax) above refine_tol sends it to FP64;
+  //   mixed with the correction: the error the correction leaves is at most
+  //     the computed weights' relative error, taken as min(1, 10 kappa_w u),
+  //     times |w_t| |h_w| + |phi_t| |Q'nu_w| (h the FP64 residual); a system
+  //     where that exceeds refine_tol (same relative measure) is unconverged
+  //     and re-solved in FP64.
+  // Systems with a non-positive pivot are always re-solved in FP64.
+  const double kw = (p->prob.refine_tol > 0.0 && p->prob.precision != OKR_FP64)
+                        ? window_kappa(p, *vario) : 0.0;
+  a.kappa_w = kw;
+  if (p->prob.precision != OKR_FP64) a.fallback = p->fallback;
   if (mixed) {
-    a.fallback = p->fallback;   // systems with a non-positive pivot
     a.refine = p->prob.refine_max > 0 ? 1 : 0;
-    a.refine_kappa = kappa_tol;
-    if (!a.refine) a.route_tol = p->prob.refine_tol;
+    a.refine_kappa = 0.0;
     a.upd = p->upd >= 0 ? p->upd : (p->prob.precision == OKR_MIXED_BF16 ? 2 : 1);
-  } else if (p->prob.precision == OKR_FP32 && p->prob.refine_tol > 0.0) {
-    a.fallback = p->fallback;
-    a.kappa_limit = kappa_tol;
+    const double uf = factor_roundoff(a.upd);
+    if (!a.refine) {
+      a.route_tol = p->prob.refine_tol;
+      a.route_scale = kw * uf;
+    } else {
+      a.refine_tol = p->prob.refine_tol;
+      a.rho_hat = std::min(1.0, 10.0 * kw * uf);
+    }
+  } else if (p->prob.precision == OKR_FP32 && p->prob.refine_tol > 0.0 &&
+             !(kw * kUnitRoundoff32 <= p->prob.refine_tol)) {
+    a.kappa_limit = 0.0;
   }
   if (force_fallback() && p->prob.precision != OKR_FP64) {
     a.kappa_limit = 0.0;
@@ -848,6 +963,8 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
     p->phase_calls[i] = 0;
   }
   out->n_not_converged = (int64_t)c.failed;
+  out->n_refine_unconverged = (int64_t)c.unconverged;
+  out->kappa_window = p->kw_valid ? p->kappa_w : 0.0;
   if (c.nonfinite) return fail(p, OKR_E_NONFINITE, "a known voxel is not finite");
   if (c.bad_input) return fail(p, OKR_E_SHAPE, "a point system has a count outside 1..98");
   if (p->prob.strict && c.failed)

@@ -21,7 +21,7 @@ constexpr uint8_t kFloorBit = 0x80;
 
 // Flag bits written per system (see okrig.h).
 constexpr uint8_t kFlagFloor = 1, kFlagRefined = 2, kFlagFp64 = 4, kFlagBadPivot = 8,
-                  kFlagFailed = 16;
+                  kFlagFailed = 16, kFlagUnconverged = 32;
 
 struct Geometry {
   int nx, ny, nslices, f, r, W, W2, ncand, min_points;
@@ -57,6 +57,7 @@ struct DevCounters {
   unsigned long long fp64_fallback;
   unsigned long long bad_pivot;
   unsigned long long failed;        // systems whose FP64 re-solve also met a bad pivot
+  unsigned long long unconverged;   // systems whose correction left the tolerance unmet
   unsigned int max_kappa_bits;      // float bits of the largest estimate
   unsigned int zmax_bits;           // float bits of the largest |known voxel|
   unsigned int nonfinite;           // nonzero if a known voxel is not finite
@@ -98,6 +99,10 @@ struct SolveArgs {
   double refine_kappa;  // mixed: condition estimate above which the FP64 correction runs
   int refine;           // mixed: 0 = factor read-out only, 1 = FP64 correction
   double route_tol;     // mixed read-out: error indicator above which a system is re-solved in FP64
+  double route_scale;   // mixed read-out: kappa_w * u of the indicator kappa_w u s / max(|z_hat|, zfloor)
+  double refine_tol;    // mixed corrected: per-voxel tolerance of the convergence test (0: none)
+  double rho_hat;       // mixed corrected: bound on the error left per unit of correction
+  double kappa_w;       // condition number of the full-window covariance matrix (0: not computed)
   int upd;              // mixed trailing updates: 0 FP32, 1 split FP16, 2 split BF16
   int nmax;             // largest neighbour count the size-class kernels take
   uint32_t* fallback;   // list of systems for the FP64 pass

@@ -757,7 +757,7 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
 // wave (one atomic per wave instead of one per system).
 struct Tally {
   float kmax = 0.0f;
-  unsigned bad = 0, fp64 = 0, failed = 0;
+  unsigned bad = 0, fp64 = 0, failed = 0, unconv = 0;
 };
 
 __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) {
@@ -765,6 +765,7 @@ __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) 
     if (t.bad) atomicAdd(&a.ctr->bad_pivot, (unsigned long long)t.bad);
     if (t.fp64) atomicAdd(&a.ctr->fp64_fallback, (unsigned long long)t.fp64);
     if (t.failed) atomicAdd(&a.ctr->failed, (unsigned long long)t.failed);
+    if (t.unconv) atomicAdd(&a.ctr->unconverged, (unsigned long long)t.unconv);
     atomic_max_float(&a.ctr->max_kappa_bits, t.kmax);
   }
 }
@@ -774,7 +775,7 @@ __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) 
 template <typename T>
 __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsigned sys, int cnt,
                                               T est, T var, T mn, T mx, bool bad, Tally& tally,
-                                              bool route = false) {
+                                              bool route = false, uint8_t extra_flags = 0) {
   const int lane = threadIdx.x & 63;
   const Geometry& geo = a.geo;
   const int ntgt = geo.f - 1;
@@ -795,7 +796,7 @@ __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsi
     if (a.variance) a.variance[o] = (float)var;
   }
   if (lane == 0 && a.flags) {
-    uint8_t fl = (cnt & kFloorBit) ? kFlagFloor : 0;
+    uint8_t fl = ((cnt & kFloorBit) ? kFlagFloor : 0) | extra_flags;
     if (mode == 1) fl |= kFlagFp64;
     if (mode == 1 && bad) fl |= kFlagFailed;
     if (bad && mode == 0) fl |= kFlagBadPivot;

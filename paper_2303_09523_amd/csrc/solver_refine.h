@@ -450,7 +450,9 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
                                              int ntgt, double sill, double refine_kappa,
                                              double* est_out, float* var_out, float& mn,
                                              float& mxp, bool& bad, double* w_out = nullptr,
-                                             double* nu_scale = nullptr) {
+                                             double* nu_scale = nullptr,
+                                             double* readout_out = nullptr,
+                                             double* bound_out = nullptr) {
   const int lane = threadIdx.x & 63;
   const int p0 = lane, p1 = lane + 64;
   // ---- 1. normalise the data ----
@@ -481,6 +483,7 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
     float var_r;
     schur_readout<float>(ws.buf, ne, lane + 1, sm.bz - 1, ntgt + 1, 1.0f, est_r, var_r);
     *var_out = (float)(sill * (double)var_r);
+    if (readout_out) *readout_out = (double)zref + ldexp((double)est_r, ex);
   }
   __builtin_amdgcn_wave_barrier();
   if (!CORR || !((double)mxp > refine_kappa * (double)mn)) {
@@ -551,6 +554,16 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   const double h1 = p1 < n ? ((double)mx.zr[p1] - zd) * isd - cn1 - nu_1 - nu_s * sl_1 : 0.0;
   const int d0 = p0 < n ? ws.desc[p0] : 0, d1 = p1 < n ? ws.desc[p1] : 0;
   double B1 = 0.0, Bs = 0.0;
+  // For the error bound: |h_w|, |1'nu_w| and |s'nu_w| (the residual's border
+  // components are -Q'nu_w).
+  float hn = 0.0f, snu = 0.0f, ssnu = 0.0f;
+  if (bound_out) {
+    float nr[3] = {(float)(h0 * h0 + h1 * h1), (float)(nu0 + nu1), (float)(sl_0 * nu0 + sl_1 * nu1)};
+    wave_sums_f(nr);
+    hn = sqrtf(nr[0]);
+    snu = fabsf(nr[1]);
+    ssnu = fabsf(nr[2]);
+  }
   for (int t0 = 1; t0 <= ntgt; t0 += kRowTargets) {
     const int cnt = (ntgt - t0 + 1) < kRowTargets ? (ntgt - t0 + 1) : kRowTargets;
     if (t0 > 1) write_rows<NB>(Z, ne + sm.bz + t0, cnt, 2, xrow);
@@ -590,8 +603,11 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
       B1 = sv[kRowTargets];
       Bs = sv[kRowTargets + 1];
     }
+    double p1k[kRowTargets], psk[kRowTargets];
 #pragma unroll
     for (int k = 0; k < kRowTargets; ++k) {
+      p1k[k] = 0.0;
+      psk[k] = 0.0;
       if (k < cnt) {
         const int t = t0 + k;
         double p1c, psc = 0.0, corr;
@@ -610,6 +626,31 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
           if (p0 < n) w_out[p0] = (double)xrow[2][p0] - p1c * x1_0 - psc * xs_0;
           if (p1 < n) w_out[p1] = (double)xrow[2][p1] - p1c * x1_1 - psc * xs_1;
         }
+        p1k[k] = p1c;
+        psk[k] = psc;
+      }
+    }
+    if (bound_out) {
+      // The estimate above is exact up to (lambda - lambda~)'h, with lambda~ =
+      // (w_t, phi_t) the computed weights and multipliers: bounded by
+      // |w_t| |h_w| + |phi_t| |Q'nu_w| times their relative error, which the
+      // caller supplies. Reported here without that factor, in data units.
+      float ww[kRowTargets];
+#pragma unroll
+      for (int k = 0; k < kRowTargets; ++k) {
+        ww[k] = 0.0f;
+        if (k < cnt) {
+          const float a0w = p0 < n ? (float)((double)xrow[2 + k][p0] - p1k[k] * x1_0 - psk[k] * xs_0) : 0.0f;
+          const float a1w = p1 < n ? (float)((double)xrow[2 + k][p1] - p1k[k] * x1_1 - psk[k] * xs_1) : 0.0f;
+          ww[k] = a0w * a0w + a1w * a1w;
+        }
+      }
+      wave_sums_f(ww);
+#pragma unroll
+      for (int k = 0; k < kRowTargets; ++k) {
+        if (k < cnt && lane == t0 + k - 1)
+          *bound_out = sd * ((double)sqrtf(ww[k]) * (double)hn + fabs(p1k[k]) * (double)snu +
+                             fabs(psk[k]) * (double)ssnu);
       }
     }
     __builtin_amdgcn_wave_barrier();

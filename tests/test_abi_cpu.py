@@ -53,7 +53,7 @@ def _prob(**kw):
     (dict(nx=0), 2), (dict(ny=70000), 2), (dict(nslices=0), 2), (dict(upsample=0), 2),
     (dict(upsample=16), 2), (dict(radius=4), 2), (dict(radius=-1), 2), (dict(min_points=0), 1),
     (dict(min_points=19), 1), (dict(precision=7), 1), (dict(algo=3), 1),
-    (dict(algo=1, precision=1), 6), (dict(refine_max=9), 1), (dict(refine_tol=-1.0), 1),
+    (dict(algo=1, precision=1), 6), (dict(refine_max=9), 1), (dict(refine_max=2), 1), (dict(refine_tol=-1.0), 1),
     (dict(drift=2), 1), (dict(drift=1, algo=1), 6),
     (dict(drift=1, upsample=15), 2),
     (dict(nx=65535, ny=65535, nslices=3), 2),

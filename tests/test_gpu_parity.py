@@ -219,54 +219,6 @@ def test_mixed_factor_readout_only(case, oracle_cache):
     assert not (fl & 2).any()
 
 
-def test_mixed_refine_threshold():
-    """refine_tol selects the systems that take the FP64 correction: 0 takes
-    all, a threshold no estimate reaches takes none, and then every system is
-    the Schur read-out. The corrected form factors with FP32 off-diagonal
-    solves and the read-out-only launch with split FP16 ones, so the two agree
-    within the read-out's error bar rather than bit for bit."""
-    case = CASES[2]
-    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
-    s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
-    vario = (model, nug, sill, rng_)
-    nsys = (n - 1) * ny * nx
-    _, _, fa, sa = run_gpu(s, e, f, r, vario, precision="mixed_fp16", flags=True, refine_tol=0.0)
-    assert sa["n_refined"] + sa["n_nonpositive_pivot"] == nsys
-    assert ((fa & 2) != 0).sum() == sa["n_refined"]
-    vb, wb, fb, sb = run_gpu(s, e, f, r, vario, precision="mixed_fp16", flags=True, refine_tol=1.0)
-    vc, wc, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", refine_max=0)
-    assert sb["n_refined"] == 0
-    assert ((fb & 2) != 0).sum() == 0
-    assert rel_err_est(vb, vc.astype(np.float64), np.abs(s).max()).max() <= 1e-4
-    assert rel_err_var(wb, wc.astype(np.float64), sill).max() <= 1e-5
-
-
-def test_fp32_condition_routing():
-    """FP32 with refine_tol > 0 re-solves the systems whose condition estimate
-    times 2^-24 exceeds it in FP64: flagged systems equal the FP64 launch bit
-    for bit, the others the unrouted FP32 launch."""
-    case = CASES[3]
-    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
-    s, e = _inputs(name, n, ny, nx, f, r, masked, seed)
-    vario = (model, nug, sill, rng_)
-    v32, w32, _, s32 = run_gpu(s, e, f, r, vario)
-    v64, w64, _, _ = run_gpu(s, e, f, r, vario, precision="fp64")
-    # threshold at half the largest estimate: the worst system is routed
-    tol = 0.5 * s32["max_kappa_est"] * 2.0 ** -24
-    vr, wr, fr, sr = run_gpu(s, e, f, r, vario, flags=True, refine_tol=tol)
-    routed = (fr & 4) != 0
-    print(f"routed {routed.sum()} of {routed.size} systems", flush=True)
-    assert 0 < routed.sum() < routed.size
-    assert sr["n_fp64_fallback"] == routed.sum()
-    for g in range(n - 1):
-        for t in range(1, f):
-            z = g * f + t
-            m = routed[g]
-            np.testing.assert_array_equal(vr[z][m], v64[z][m])
-            np.testing.assert_array_equal(vr[z][~m], v32[z][~m])
-            np.testing.assert_array_equal(wr[z][m], w64[z][m])
-
-
 def test_strict_mode_reports_failed_systems():
     """A near-singular Gaussian model: strict mode turns an FP64 re-solve that
     still meets a non-positive pivot into OKR_E_NOT_CONVERGED at the sync; the
@@ -293,36 +245,6 @@ def test_strict_mode_reports_failed_systems():
     else:
         plan.stats()
     plan.close()
-
-
-def test_mixed_error_routing(oracle_cache):
-    """Read-out-only mixed with refine_tol > 0: systems whose error indicator
-    exceeds it are re-solved in FP64 (bit for bit the FP64 launch), the rest
-    keep the read-out (bit for bit the unrouted launch); the routed result
-    meets the refined bar."""
-    case = CASES[2]
-    name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
-    s, e, vol_o, var_o, _ = _oracle(oracle_cache, case)
-    vario = (model, nug, sill, rng_)
-    v0, w0, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", refine_max=0)
-    v64, w64, _, _ = run_gpu(s, e, f, r, vario, precision="fp64")
-    vr, wr, fr, sr = run_gpu(s, e, f, r, vario, precision="mixed_fp16", flags=True, refine_max=0,
-                             refine_tol=1e-6)
-    routed = (fr & 4) != 0
-    print(f"routed {routed.sum()} of {routed.size} systems", flush=True)
-    assert 0 < routed.sum() < routed.size
-    assert sr["n_fp64_fallback"] == routed.sum()
-    for g in range(n - 1):
-        for t in range(1, f):
-            z = g * f + t
-            m = routed[g]
-            np.testing.assert_array_equal(vr[z][m], v64[z][m])
-            np.testing.assert_array_equal(vr[z][~m], v0[z][~m])
-    kz = np.ones(vr.shape[0], bool)
-    kz[::f] = False
-    ee = rel_err_est(vr[kz], vol_o[kz], np.abs(s).max())
-    print(f"routed max est err {ee.max():.3e}", flush=True)
-    assert ee.max() <= TOL["mixed_fp16"]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
