@@ -358,13 +358,29 @@ def krige_sample(slices, edge, f: int, r: int, vario, gs, ys, xs, min_points: in
     vario = _vtuple(vario)
     slices = np.asarray(slices, dtype=np.float32)
     gs = np.asarray(gs, dtype=np.int64)
-    lo, hi = slices[gs], slices[gs + 1]
-    if edge is None:
-        elo = ehi = None
-    else:
-        elo, ehi = edge[gs], edge[gs + 1]
-    return _systems(lo, hi, elo, ehi, np.asarray(ys, dtype=np.int64), np.asarray(xs, dtype=np.int64),
-                    f, list(range(1, f)), r, vario, min_points, drift=drift)
+    ys = np.asarray(ys, dtype=np.int64)
+    xs = np.asarray(xs, dtype=np.int64)
+    _, H, Wd = slices.shape
+    S = gs.shape[0]
+    nc = 2 * (2 * r + 1) ** 2
+    est = np.empty((S, f - 1)); var = np.empty((S, f - 1))
+    ns = np.empty(S, dtype=np.int64)
+    kept = np.empty((S, nc), dtype=bool)
+    # one gap at a time, its two slices shared by every system of the gap
+    for g in np.unique(gs):
+        sel = np.nonzero(gs == g)[0]
+        k = sel.shape[0]
+        lo = np.broadcast_to(slices[g], (k, H, Wd))
+        hi = np.broadcast_to(slices[g + 1], (k, H, Wd))
+        if edge is None:
+            elo = ehi = None
+        else:
+            elo = np.broadcast_to(edge[g], (k, H, Wd))
+            ehi = np.broadcast_to(edge[g + 1], (k, H, Wd))
+        e_, v_, n_, k_ = _systems(lo, hi, elo, ehi, ys[sel], xs[sel], f, list(range(1, f)), r,
+                                  vario, min_points, drift=drift)
+        est[sel], var[sel], ns[sel], kept[sel] = e_, v_, n_, k_
+    return est, var, ns, kept
 
 
 # ----------------------------------------------------------------------------
