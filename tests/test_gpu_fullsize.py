@@ -12,20 +12,25 @@ from _gpu_util import rel_err_est, rel_err_var
 
 pytestmark = pytest.mark.gpu
 
-# (workload, precision, refine_max, per-voxel bar, normwise bar)
+# (workload, precision, refine_max, refine_tol, per-voxel bar). The refined
+# mixed paths carry the per-voxel bars they are run at (1e-5 for the large
+# and edge-preserved workloads, the mixed bar 1e-4 with the ill-conditioned
+# Gaussian model); the read-out-only and FP32 paths are not claimed at 1e-5
+# (their per-voxel error is about 5e-5 there) and carry 1e-4.
 FULL = [
-    ("edge_32x256", "mixed_fp16", 0, 1e-4, 1e-5),
-    ("edge_32x256", "fp32", 0, 1e-4, 1e-5),
-    ("precision_48x384", "mixed_fp16", 1, 1e-4, 1e-5),
-    ("precision_48x384", "fp64", 0, 1.2e-7, 1.2e-7),
-    ("large_160x512", "mixed_fp16", 0, 1e-4, 1e-5),
+    ("edge_32x256", "mixed_fp16", 1, 1e-5, 1e-5),
+    ("edge_32x256", "mixed_fp16", 0, 0.0, 1e-4),
+    ("edge_32x256", "fp32", 0, 0.0, 1e-4),
+    ("precision_48x384", "mixed_fp16", 1, 1e-4, 1e-4),
+    ("precision_48x384", "fp64", 0, 0.0, 1.2e-7),
+    ("large_160x512", "mixed_fp16", 0, 0.0, 1e-4),
     ("large_160x512", "mixed_fp16", 1, 1e-5, 1e-5),
 ]
 
 
-@pytest.mark.parametrize("name,precision,refine_max,bar,bar_nw", FULL,
+@pytest.mark.parametrize("name,precision,refine_max,refine_tol,bar", FULL,
                          ids=[f"{f[0]}-{f[1]}-r{f[2]}" for f in FULL])
-def test_full_size_sampled(name, precision, refine_max, bar, bar_nw):
+def test_full_size_sampled(name, precision, refine_max, refine_tol, bar):
     import torch
     import paper_2303_09523_amd as P
     w = W.workload(name)
@@ -34,7 +39,7 @@ def test_full_size_sampled(name, precision, refine_max, bar, bar_nw):
     st = torch.from_numpy(s).cuda()
     et = torch.from_numpy(e).cuda() if e is not None else None
     plan = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, precision, "batched",
-                  refine_max=refine_max)
+                  refine_max=refine_max, refine_tol=refine_tol)
     vol = torch.empty(plan.out_shape(), dtype=torch.float32, device="cuda")
     var = torch.empty_like(vol)
     plan.autotune(st, w.vario, et, volume=vol, variance=var)
@@ -43,6 +48,8 @@ def test_full_size_sampled(name, precision, refine_max, bar, bar_nw):
     plan.execute(st, w.vario, et, volume=vol, variance=var)
     stats = plan.stats()
     plan.close()
+    print(f"  FP64 re-solved {stats['n_fp64_fallback']}, unconverged "
+          f"{stats['n_refine_unconverged']}", flush=True)
     assert stats["n_systems"] == w.systems and sum(stats["bucket"]) == w.systems
     assert torch.equal(vol[::w.upsample].cpu(), torch.from_numpy(s))
     assert (var[::w.upsample] == 0).all()
@@ -65,4 +72,16 @@ def test_full_size_sampled(name, precision, refine_max, bar, bar_nw):
     nw = np.abs(vn - est_o).max() / np.abs(est_o).max()
     print(f"  sampled {ee.size} voxels: est {ee.max():.3e} var {ev.max():.3e} normwise {nw:.3e}",
           flush=True)
-    assert ee.max() <= bar and nw <= bar_nw and ev.max() <= max(bar, 1e-5)
+    assert ee.max() <= bar and ev.max() <= max(bar, 1e-5)
+    if name == "large_160x512" and refine_max == 1:
+        # every voxel of one whole gap in the middle of the stack
+        gmid = (w.nslices - 1) // 2
+        vo, va, _ = O.krige_volume(s, e, w.upsample, w.radius, vario, gaps=[gmid])
+        zs = slice(gmid * w.upsample + 1, (gmid + 1) * w.upsample)
+        vg = vol[zs].cpu().numpy().astype(np.float64)
+        wg = var[zs].cpu().numpy().astype(np.float64)
+        eg = rel_err_est(vg, vo[zs], zmax)
+        evg = rel_err_var(wg, va[zs], w.vario.sill)
+        print(f"  gap {gmid}, {eg.size} voxels: est {eg.max():.3e} var {evg.max():.3e}",
+              flush=True)
+        assert eg.max() <= bar and evg.max() <= 1e-5

@@ -1,14 +1,16 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Error measures: per voxel, |z_hat - z*| / max(|z*|, 0.01 Zmax) for the
-estimate and |s2 - s2*| / sill for the variance; normwise,
-max |z_hat - z*| / max |z*|. Bars:
-  * FP32 paths (batched and plain per-voxel): normwise <= 1e-5 and per voxel
-    <= 1e-4. Their per-voxel error is set by FP32 conditioning (about
-    kappa * u, kappa up to ~330 for the 7x7x2 windows), which is why the
-    strict per-voxel 1e-5 bar is carried by the refined paths below.
-  * mixed FP16 (split MFMA + FP64-residual correction): per voxel <= 1e-5.
-  * mixed BF16: per voxel <= 1e-4.
+estimate and |s2 - s2*| / sill for the variance (the bars); normwise,
+max |z_hat - z*| / max |z*| (printed, and asserted only as an extra check on
+the FP32 paths). Bars:
+  * FP32 paths (batched and plain per-voxel) and the mixed read-out: per
+    voxel <= 1e-4. Their per-voxel error is set by FP32 border solves over an
+    FP32 factor (about 5e-5 on 7x7x2 windows), so they are not claimed at
+    1e-5; the 1e-5 bar is carried by the refined mixed paths.
+  * mixed FP16 with the FP64-residual correction (the plan default,
+    refine_max = 1): per voxel <= 1e-5.
+  * mixed BF16 with the correction: per voxel <= 1e-4.
   * FP64: per voxel <= 1.2e-7 (outputs are written as float32).
   * integer selection: bit-exact.
 """
