@@ -283,6 +283,30 @@ okr_status okr_stats_get(okr_plan* plan, okr_stats* out);
 
 okr_status okr_plan_destroy(okr_plan* plan);
 
+/* okr_execute without a plan and without any allocation, for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same arguments and results as
+ * okr_plan_create + okr_execute on the given problem (identical kernels;
+ * the launch shape is the untuned default and no graph is used), except:
+ *   - the workspace is a static device array of the library, 26.2 MB per GPU
+ *     it runs on, held until the process ends: problems of at most 2^20
+ *     (column, gap) systems ((nslices-1)*nx*ny <= 1048576), larger ones get
+ *     OKR_E_SHAPE before any device work;
+ *   - every call on one GPU shares that array: calls that overlap on one GPU
+ *     (other streams, other threads) race and must be serialised by the
+ *     caller; each call clears what it needs and leaves the last call's
+ *     contents behind;
+ *   - device-detected errors are not latched in a plan: with d_status
+ *     (device int32, nullable) the call writes, stream-ordered, the status
+ *     okr_stats_get would return (OKR_OK, OKR_E_NONFINITE, or with strict
+ *     OKR_E_NOT_CONVERGED).
+ * hip_stream is a hipStream_t (NULL = the default stream); work is
+ * asynchronous. Argument errors are returned before any device work. */
+okr_status okr_execute_noalloc(const okr_problem* problem, void* hip_stream,
+                               const okr_variogram* vario, const float* d_slices,
+                               const uint8_t* d_edge, float* d_volume, float* d_variance,
+                               uint8_t* d_flags, int32_t* d_status);
+
 /* Profiling: when enabled, every phase launch is bracketed by HIP events on the
  * plan's stream and okr_stats_get reports the summed device time per phase
  * (then clears it). Off by default; costs one event pair per phase. */

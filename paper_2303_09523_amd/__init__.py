@@ -15,7 +15,7 @@ from typing import Optional
 from . import _lib
 from ._lib import OkrError, load  # noqa: F401
 
-__all__ = ["Plan", "krige", "select", "OkrError", "load", "LosoLoss"]
+__all__ = ["Plan", "krige", "select", "execute_noalloc", "OkrError", "load", "LosoLoss"]
 
 
 def _torch():
@@ -233,6 +233,28 @@ def krige(slices, vario, upsample: int, radius: int, edge=None, min_points: int 
     vol, var, _ = plan.execute(slices, vario, edge, want_variance=want_variance)
     plan.close()
     return vol, var
+
+
+def execute_noalloc(slices, vario, upsample: int, radius: int, volume, variance=None, edge=None,
+                    flags=None, status=None, min_points: int = 4, precision: str = "fp32",
+                    algo: str = "batched", refine_tol: float = 0.0, refine_max: int = 1,
+                    strict: bool = False, drift: str = "none", stream=None):
+    """okr_execute_noalloc: one reconstruction into caller tensors with the
+    library's static workspace (no plan, no device allocation). status, if
+    given, is a CUDA int32 tensor of one element that receives the
+    device-detected status."""
+    torch = _torch()
+    n, ny, nx = slices.shape
+    drifts = {"none": 0, "linear_z": 1}
+    prob = _lib.Problem(nx, ny, n, upsample, radius, min_points, _lib.PRECISIONS[precision],
+                        _lib.ALGOS[algo], refine_tol, refine_max, int(strict),
+                        drifts[drift] if isinstance(drift, str) else int(drift))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    v = _as_vario(vario)
+    _lib.check(load().okr_execute_noalloc(C.byref(prob), C.c_void_p(stream.cuda_stream),
+                                          C.byref(v), _ptr(slices), _ptr(edge), _ptr(volume),
+                                          _ptr(variance), _ptr(flags), _ptr(status)))
 
 
 def select(edge, nslices, ny, nx, radius, min_points=4):

@@ -25,7 +25,7 @@ EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
             "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling",
             "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning",
-            "okr_krige_points", "okr_marching_cubes"]
+            "okr_krige_points", "okr_marching_cubes", "okr_execute_noalloc"]
 
 
 class Variogram(C.Structure):
@@ -88,6 +88,8 @@ def load():
         "okr_marching_cubes": (C.c_int32, [VP, VP, C.c_float, VP, VP, C.c_int64,
                                            P(C.c_int64)]),
         "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double)]),
+        "okr_execute_noalloc": (C.c_int32, [P(Problem), VP, P(Variogram), VP, VP, VP, VP, VP,
+                                            VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

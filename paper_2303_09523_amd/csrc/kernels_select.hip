@@ -271,6 +271,18 @@ hipError_t launch_tables(const Vario& v, const Geometry& g, TableSet t, hipStrea
   return hipGetLastError();
 }
 
+// Device-detected status of the last execute on these counters, as an
+// okr_status value: non-finite input, then (strict) an FP64 re-solve that met a
+// non-positive pivot.
+__global__ void status_kernel(const DevCounters* c, int strict, int32_t* out) {
+  if (threadIdx.x == 0) *out = c->nonfinite ? 3 : ((strict && c->failed) ? 7 : 0);
+}
+
+hipError_t launch_status(const DevCounters* c, int strict, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(status_kernel, dim3(1), dim3(64), 0, s, c, strict, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(DevCounters* c, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(kHist), 0, s, c);
   return hipGetLastError();

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -250,6 +251,36 @@ void free_plan(okr_plan* p) {
   delete p;
 }
 
+// Problem, stream, geometry, selection rule and device of a plan (no
+// allocation).
+okr_status init_plan_shape(okr_plan* p, const okr_problem* problem, void* hip_stream) {
+  p->prob = *problem;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  okr::Geometry& g = p->geo;
+  g.nx = problem->nx;
+  g.ny = problem->ny;
+  g.nslices = problem->nslices;
+  g.f = problem->upsample;
+  g.r = problem->radius;
+  g.W = 2 * g.r + 1;
+  g.W2 = g.W * g.W;
+  g.ncand = 2 * g.W2;
+  g.min_points = problem->min_points;
+  g.drift = problem->drift;
+  g.plane = (long long)g.nx * g.ny;
+  g.nsys = g.plane * (g.nslices > 1 ? g.nslices - 1 : 0);
+  build_rule(g.r, &p->rule);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return OKR_E_DEVICE;
+  }
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+      cu > 0)
+    p->num_cu = cu;
+  return OKR_OK;
+}
+
 okr::TableSet tables_of(okr_plan* p) {
   okr::TableSet t;
   t.tc_d = p->tabs;
@@ -378,31 +409,11 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
   if (st != OKR_OK) return st;
   okr_plan* p = new (std::nothrow) okr_plan();
   if (!p) return OKR_E_OOM;
-  p->prob = *problem;
-  p->stream = static_cast<hipStream_t>(hip_stream);
-  okr::Geometry& g = p->geo;
-  g.nx = problem->nx;
-  g.ny = problem->ny;
-  g.nslices = problem->nslices;
-  g.f = problem->upsample;
-  g.r = problem->radius;
-  g.W = 2 * g.r + 1;
-  g.W2 = g.W * g.W;
-  g.ncand = 2 * g.W2;
-  g.min_points = problem->min_points;
-  g.drift = problem->drift;
-  g.plane = (long long)g.nx * g.ny;
-  g.nsys = g.plane * (g.nslices > 1 ? g.nslices - 1 : 0);
-  build_rule(g.r, &p->rule);
-  if (hipGetDevice(&p->device) != hipSuccess) {
-    (void)hipGetLastError();
+  if ((st = init_plan_shape(p, problem, hip_stream)) != OKR_OK) {
     free_plan(p);
-    return OKR_E_DEVICE;
+    return st;
   }
-  int cu = 0;
-  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
-      cu > 0)
-    p->num_cu = cu;
+  const okr::Geometry& g = p->geo;
   const size_t nsys = (size_t)std::max<long long>(g.nsys, 1);
   if ((st = dev_alloc(p, &p->ctr, 1)) != OKR_OK ||
       (st = dev_alloc(p, &p->tabs, 4 * okr::kTcSize + 4 * okr::kT0Size)) != OKR_OK ||
@@ -457,9 +468,9 @@ double host_cov(const okr_variogram& v, double h) {
 
 // Smallest and largest eigenvalue of a symmetric matrix (cyclic Jacobi
 // rotations in FP64; a is overwritten).
-void sym_eig_range(std::vector<double>& a, int n, double* lmin, double* lmax) {
+void sym_eig_range(double* a, int n, double* lmin, double* lmax) {
   double fro = 0.0;
-  for (double x : a) fro += x * x;
+  for (int i = 0; i < n * n; ++i) fro += a[i] * a[i];
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0;
     for (int i = 0; i < n; ++i)
@@ -503,7 +514,8 @@ double window_kappa(okr_plan* p, const okr_variogram& v) {
     return p->kappa_w;
   const okr::Geometry& g = p->geo;
   const int n = g.ncand;
-  std::vector<double> pts(3 * n), a((size_t)n * n);
+  double pts[3 * okr::kMaxCand];
+  double a[okr::kMaxCand * okr::kMaxCand];
   for (int c = 0; c < n; ++c) {
     const int sl = c / g.W2, o = c % g.W2;
     pts[3 * c] = o % g.W - g.r;
@@ -970,6 +982,94 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
   if (p->prob.strict && c.failed)
     return fail(p, OKR_E_NOT_CONVERGED, "a system met a non-positive pivot in FP64 as well");
   return OKR_OK;
+}
+
+}  // extern "C"
+
+// ---- okr_execute_noalloc: okr_execute with a static workspace ----
+namespace {
+
+// The workspace of one execute of up to kStaticMaxSystems (column, gap)
+// systems, in a file-scope device array that every GPU the library runs on
+// holds until the process ends. Layout (each part 256-byte aligned): counters,
+// FP64 and FP32 tables, full-window pattern weights, then per system the
+// kept mask (2 x u64), the count byte, the size-sorted permutation (u32) and
+// the FP64 re-solve list (u32).
+constexpr long long kStaticMaxSystems = 1LL << 20;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kOffCtr = 0;
+constexpr size_t kOffTabs = kOffCtr + align256(sizeof(okr::DevCounters));
+constexpr size_t kOffTabsF = kOffTabs + align256(sizeof(double) * (4 * okr::kTcSize + 4 * okr::kT0Size));
+constexpr size_t kOffPattern = kOffTabsF + align256(sizeof(float) * (okr::kTcSize + okr::kT0Size));
+constexpr size_t kOffBits =
+    kOffPattern + align256(sizeof(double) * ((okr::kMaxUpsample - 1) * okr::kMaxCand + okr::kMaxUpsample));
+constexpr size_t kOffCount = kOffBits + align256(sizeof(uint64_t) * 2 * kStaticMaxSystems);
+constexpr size_t kOffPerm = kOffCount + align256(kStaticMaxSystems);
+constexpr size_t kOffFallback = kOffPerm + align256(sizeof(uint32_t) * kStaticMaxSystems);
+constexpr size_t kStaticBytes = kOffFallback + align256(sizeof(uint32_t) * kStaticMaxSystems);
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+// Device address of `scratch` per device, from hipGetSymbolAddress on the
+// first call made with that device current (the array's host-side name is
+// not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+okr_status static_workspace(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return OKR_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return OKR_E_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return OKR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+okr_status okr_execute_noalloc(const okr_problem* problem, void* hip_stream,
+                               const okr_variogram* vario, const float* d_slices,
+                               const uint8_t* d_edge, float* d_volume, float* d_variance,
+                               uint8_t* d_flags, int32_t* d_status) {
+  std::string msg;
+  okr_status st = validate_problem(problem, &msg);
+  if (st != OKR_OK) return st;
+  if (validate_vario(vario, &msg) != OKR_OK) return OKR_E_INVALID_ARG;
+  if (!d_slices || !d_volume) return OKR_E_INVALID_ARG;
+  const long long nsys =
+      (long long)problem->nx * problem->ny * (problem->nslices > 1 ? problem->nslices - 1 : 0);
+  if (nsys > kStaticMaxSystems) return OKR_E_SHAPE;
+  okr_plan p;
+  if ((st = init_plan_shape(&p, problem, hip_stream)) != OKR_OK) return st;
+  unsigned char* base = nullptr;
+  if ((st = static_workspace(p.device, &base)) != OKR_OK) return st;
+  p.ctr = reinterpret_cast<okr::DevCounters*>(base + kOffCtr);
+  p.tabs = reinterpret_cast<double*>(base + kOffTabs);
+  p.tabs_f = reinterpret_cast<float*>(base + kOffTabsF);
+  p.pattern_w = reinterpret_cast<double*>(base + kOffPattern);
+  p.bits = reinterpret_cast<uint64_t*>(base + kOffBits);
+  p.count = base + kOffCount;
+  p.perm = reinterpret_cast<uint32_t*>(base + kOffPerm);
+  p.fallback = reinterpret_cast<uint32_t*>(base + kOffFallback);
+  st = enqueue_execute(&p, p.stream, vario, d_slices, d_edge, d_volume, d_variance, d_flags);
+  if (st == OKR_OK && d_status &&
+      okr::launch_status(p.ctr, problem->strict, d_status, p.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    st = OKR_E_DEVICE;
+  }
+  // the plan's pointers belong to the static workspace: nothing to free
+  p.ctr = nullptr; p.tabs = nullptr; p.tabs_f = nullptr; p.pattern_w = nullptr;
+  p.bits = nullptr; p.count = nullptr; p.perm = nullptr; p.fallback = nullptr;
+  return st;
 }
 
 }  // extern "C"

@@ -72,6 +72,7 @@ struct DevCounters {
 // ---- launchers (kernels_select.hip) ----
 hipError_t launch_tables(const Vario& v, const Geometry& g, TableSet t, hipStream_t s);
 hipError_t launch_reset(DevCounters* c, hipStream_t s);
+hipError_t launch_status(const DevCounters* c, int strict, int32_t* out, hipStream_t s);
 hipError_t launch_reset_cursors(DevCounters* c, hipStream_t s);
 hipError_t launch_place(const float* slices, float* volume, float* variance, const Geometry& g,
                         DevCounters* c, hipStream_t s);
