@@ -324,19 +324,26 @@ okr_status okr_plan_set_graph(okr_plan* plan, int32_t enable);
  * in okr_execute; flags are not written) for each candidate launch shape --
  * 1 to 4 persistent workgroups per compute unit and, for MIXED_*, the split
  * low-precision or the FP32 trailing-update arithmetic (the FP32 form is at
- * least as accurate) -- and keeps the fastest for later calls. Synchronises
- * the plan's stream. Every candidate computes the same problem; the last one
- * timed leaves its result in d_volume / d_variance. */
+ * least as accurate) -- as the median of three timed executes after one
+ * warm-up, and keeps the fastest for later calls. The choice is cached for
+ * the process, keyed by (device architecture, radius, upsample, precision,
+ * algo, refine_max, drift): a later autotune of a plan with the same key
+ * takes the cached shape without timing (okr_plan_get_tuning reports it).
+ * Synchronises the plan's stream when it times. Every candidate computes the
+ * same problem; the last one timed leaves its result in d_volume /
+ * d_variance. */
 okr_status okr_plan_autotune(okr_plan* plan, const okr_variogram* vario, const float* d_slices,
                              const uint8_t* d_edge, float* d_volume, float* d_variance);
 
 /* The plan's launch shape: workgroups per compute unit, mixed update
  * arithmetic (-1: the precision's own, 0: FP32, 1: split FP16, 2: split BF16)
- * and, after okr_plan_autotune, the time of each candidate in ms (double[8],
- * nullable; candidates in the order grid 1..4, each with the precision's own
- * then FP32 updates for MIXED_*, grid 1..4 otherwise). */
+ * and, after okr_plan_autotune, the median time of each candidate in ms
+ * (double[8], nullable; candidates in the order grid 1..4, each with the
+ * precision's own then FP32 updates for MIXED_*, grid 1..4 otherwise; the
+ * times of the run that made a cached choice), and whether the choice came
+ * from the cache (from_cache, nullable: 1 cached, 0 timed by this plan). */
 okr_status okr_plan_get_tuning(const okr_plan* plan, int32_t* grid_per_cu, int32_t* update_arith,
-                               double* cand_ms);
+                               double* cand_ms, int32_t* from_cache);
 
 const char* okr_status_string(okr_status status);
 const char* okr_plan_last_error(const okr_plan* plan);

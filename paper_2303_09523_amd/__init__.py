@@ -127,10 +127,12 @@ class Plan:
         return self.tuning()
 
     def tuning(self) -> dict:
-        g, u = C.c_int32(), C.c_int32()
+        g, u, fc = C.c_int32(), C.c_int32(), C.c_int32()
         ms = (C.c_double * 8)()
-        _lib.check(load().okr_plan_get_tuning(self._h, C.byref(g), C.byref(u), ms), self._h)
-        return {"grid_per_cu": g.value, "update_arith": u.value, "candidate_ms": list(ms)}
+        _lib.check(load().okr_plan_get_tuning(self._h, C.byref(g), C.byref(u), ms, C.byref(fc)),
+                   self._h)
+        return {"grid_per_cu": g.value, "update_arith": u.value, "candidate_ms": list(ms),
+                "from_cache": bool(fc.value)}
 
     def krige_points(self, count, offset, xyz, val, target_xyz, vario, want_weights=False):
         """FP64 ordinary kriging of explicit point sets (okr_krige_points).

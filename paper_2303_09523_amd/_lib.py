@@ -87,7 +87,8 @@ def load():
         "okr_plan_autotune": (C.c_int32, [VP, P(Variogram), VP, VP, VP, VP]),
         "okr_marching_cubes": (C.c_int32, [VP, VP, C.c_float, VP, VP, C.c_int64,
                                            P(C.c_int64)]),
-        "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double)]),
+        "okr_plan_get_tuning": (C.c_int32, [VP, P(C.c_int32), P(C.c_int32), P(C.c_double),
+                                            P(C.c_int32)]),
         "okr_execute_noalloc": (C.c_int32, [P(Problem), VP, P(Variogram), VP, VP, VP, VP, VP,
                                             VP]),
     }

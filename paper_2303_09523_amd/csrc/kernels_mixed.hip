@@ -47,6 +47,7 @@ void mixed_class_kernel(SolveArgs a) {
   __shared__ Smem<float> sm;
   __shared__ MixedSmem msm;
   __shared__ WaveScratch<float> wsa[W];
+  __shared__ ChunkStage csa[W];
   __shared__ MixedScratch msa[W];
   __shared__ f32x4 xsa[CORR ? W * area_vec4<NB>() : 1];   // each wave's area (see area_vec4)
   const double tscale = 1.0 / a.sill;
@@ -55,6 +56,7 @@ void mixed_class_kernel(SolveArgs a) {
   __syncthreads();
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveScratch<float>& ws = wsa[wid];
+  ChunkStage& cst = csa[wid];
   MixedScratch& mx = msa[wid];
   const int nb = a.nb;
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
@@ -80,14 +82,24 @@ void mixed_class_kernel(SolveArgs a) {
     const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
-    pipe_prefetch(q, a, 0, d0, d1, below);
+    unsigned sg = 0, sy = 0, sx = 0;
+    const bool staged = stage_chunk(q, a, nk, cst, sg, sy, sx);
+    if (staged)
+      pipe_prefetch_staged(q, cst, 0, d0, d1, below, ncand);
+    else
+      pipe_prefetch(q, a, 0, d0, d1, below);
     for (int k = 0; k < nk; ++k) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
       const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
       const int n = __popcll(lo) + __popcll(hi);
       pipe_commit<float>(q, ws, d0, d1, n);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
+      if (k + 1 < nk) {
+        if (staged)
+          pipe_prefetch_staged(q, cst, k + 1, d0, d1, below, ncand);
+        else
+          pipe_prefetch(q, a, k + 1, d0, d1, below);
+      }
       // nb is fixed for the launch; hidden from loop-invariant code motion so that
       // the tests on it inside the factorisation stay scalar compares per system
       // instead of lane masks held (and spilled) across the whole loop
@@ -126,10 +138,12 @@ void mixed_class_kernel(SolveArgs a) {
           tally.unconv += 1;
         }
       }
-      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally, route, extra);
+      finish_system<float>(a, 0, sys, cnt, (float)est, var, mn, mxp, bad, tally, route, extra,
+                           staged ? &cst : nullptr, k);
       if (lane == 0 && a.flags && corr && !bad) a.flags[sys] |= kFlagRefined;
       refined += (corr && !bad) ? 1 : 0;
     }
+    if (staged) flush_chunk(a, cst, nk, sg, sy, sx);
   }
   flush_tally(a, tally);
   if (lane == 0 && refined) atomicAdd(&a.ctr->refined, refined);

@@ -58,9 +58,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
 void solve_class_kernel(SolveArgs a) {
   __shared__ Smem<T> sm;
   __shared__ WaveScratch<T> wsa[class_waves<T>()];
+  __shared__ ChunkStage csa[class_waves<T>()];
   block_setup<T>(a, sm);
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   WaveScratch<T>& ws = wsa[wid];
+  ChunkStage& cst = csa[wid];
   const int nb = a.nb;
   int nlo = 16 * (NB - 1) - nb + 1, nhi = 16 * NB - nb;
   if (nlo < 1) nlo = 1;
@@ -84,14 +86,24 @@ void solve_class_kernel(SolveArgs a) {
     const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
-    pipe_prefetch(q, a, 0, d0, d1, below);
+    unsigned sg = 0, sy = 0, sx = 0;
+    const bool staged = stage_chunk(q, a, nk, cst, sg, sy, sx);
+    if (staged)
+      pipe_prefetch_staged(q, cst, 0, d0, d1, below, ncand);
+    else
+      pipe_prefetch(q, a, 0, d0, d1, below);
     for (int k = 0; k < nk; ++k) {
       const unsigned sys = __builtin_amdgcn_readlane(q.msys, k);
       const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
       const int cnt = __builtin_amdgcn_readlane(q.mcnt, k);
       const int n = __popcll(lo) + __popcll(hi);
       pipe_commit<T>(q, ws, d0, d1, n);
-      if (k + 1 < nk) pipe_prefetch(q, a, k + 1, d0, d1, below);
+      if (k + 1 < nk) {
+        if (staged)
+          pipe_prefetch_staged(q, cst, k + 1, d0, d1, below, ncand);
+        else
+          pipe_prefetch(q, a, k + 1, d0, d1, below);
+      }
       T est = 0, var = 0, mn, mx;
       bool bad;
       // nb is fixed for the launch: kept out of loop-invariant code motion, as in
@@ -99,8 +111,10 @@ void solve_class_kernel(SolveArgs a) {
       int nbs = nb;
       asm volatile("" : "+s"(nbs));
       solve_system<T, NB>(n, nbs, ws, sm, ncand, ws.buf, sill, ntgt, &est, &var, mn, mx, bad);
-      finish_system<T>(a, 0, sys, cnt, est, var, mn, mx, bad, tally);
+      finish_system<T>(a, 0, sys, cnt, est, var, mn, mx, bad, tally, false, 0,
+                       staged ? &cst : nullptr, k);
     }
+    if (staged) flush_chunk(a, cst, nk, sg, sy, sx);
   }
   flush_tally(a, tally);
 }

@@ -62,7 +62,8 @@ struct okr_plan {
   int grid_per_cu = 3;          // persistent workgroups per compute unit (autotuned)
   int upd = -1;                 // mixed trailing-update arithmetic (-1: from the precision)
   bool tuned = false;
-  double tune_ms[8] = {0};      // autotune: best time per candidate, ms
+  bool tune_cached = false;     // the shape came from the process-wide cache
+  double tune_ms[8] = {0};      // autotune: median time per candidate, ms
   // launch graph of okr_execute, keyed by its arguments
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -542,6 +543,40 @@ double factor_roundoff(int upd) {
   return upd == 2 ? std::ldexp(1.0, -16) : (upd == 1 ? std::ldexp(1.0, -22) : std::ldexp(1.0, -24));
 }
 
+// Process-wide autotune cache: the chosen launch shape per (device
+// architecture, radius, upsample, precision, algo, refine_max, drift).
+struct TuneKey {
+  char arch[64];
+  int r, f, precision, algo, refine_max, drift;
+  bool operator==(const TuneKey& o) const {
+    return std::strncmp(arch, o.arch, sizeof(arch)) == 0 && r == o.r && f == o.f &&
+           precision == o.precision && algo == o.algo && refine_max == o.refine_max &&
+           drift == o.drift;
+  }
+};
+struct TuneVal {
+  int grid, upd;
+  double ms[8];
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, TuneVal>> g_tune_cache;
+
+TuneKey tune_key(const okr_plan* p) {
+  TuneKey k{};
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess)
+    std::strncpy(k.arch, prop.gcnArchName, sizeof(k.arch) - 1);
+  else
+    (void)hipGetLastError();
+  k.r = p->geo.r;
+  k.f = p->geo.f;
+  k.precision = p->prob.precision;
+  k.algo = p->prob.algo;
+  k.refine_max = p->prob.refine_max;
+  k.drift = p->prob.drift;
+  return k;
+}
+
 // The launch sequence of okr_execute on stream `strm` (the plan's stream, or
 // the capture stream of its graph).
 okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* vario,
@@ -724,6 +759,21 @@ okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const floa
     p->tuned = true;
     return OKR_OK;
   }
+  const TuneKey key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto& e : g_tune_cache) {
+      if (e.first == key) {
+        p->grid_per_cu = e.second.grid;
+        p->upd = e.second.upd;
+        std::memcpy(p->tune_ms, e.second.ms, sizeof(p->tune_ms));
+        p->tuned = true;
+        p->tune_cached = true;
+        drop_graph(p);
+        return OKR_OK;
+      }
+    }
+  }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
   const int own_upd = p->prob.precision == OKR_MIXED_BF16 ? 2 : 1;
   struct Cand { int grid, upd; };
@@ -741,25 +791,32 @@ okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const floa
     (void)hipEventDestroy(e0);
     return fail(p, OKR_E_DEVICE, "hipEventCreate failed");
   }
+  constexpr int kReps = 3;
   double best = 1e300;
   Cand pick = {p->grid_per_cu, p->upd};
   for (size_t i = 0; i < cands.size() && st == OKR_OK; ++i) {
     p->grid_per_cu = cands[i].grid;
     p->upd = cands[i].upd;
     st = enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, nullptr);
-    if (st != OKR_OK) break;
-    (void)hipEventRecord(e0, p->stream);
-    st = enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, nullptr);
-    (void)hipEventRecord(e1, p->stream);
-    if (st != OKR_OK) break;
-    float ms = 0.0f;
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = fail(p, OKR_E_DEVICE, "autotune timing failed");
-      break;
+    double ms[kReps];
+    for (int k = 0; k < kReps && st == OKR_OK; ++k) {
+      (void)hipEventRecord(e0, p->stream);
+      st = enqueue_execute(p, p->stream, vario, d_slices, d_edge, d_volume, d_variance, nullptr);
+      (void)hipEventRecord(e1, p->stream);
+      if (st != OKR_OK) break;
+      float t = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+        st = fail(p, OKR_E_DEVICE, "autotune timing failed");
+        break;
+      }
+      ms[k] = t;
     }
-    if (i < 8) p->tune_ms[i] = ms;
-    if (ms < best) {
-      best = ms;
+    if (st != OKR_OK) break;
+    std::sort(ms, ms + kReps);
+    const double med = ms[kReps / 2];
+    if (i < 8) p->tune_ms[i] = med;
+    if (med < best) {
+      best = med;
       pick = cands[i];
     }
   }
@@ -769,18 +826,26 @@ okr_status okr_plan_autotune(okr_plan* p, const okr_variogram* vario, const floa
   p->upd = pick.upd;
   p->use_graph = graph;
   p->profiling = prof;
-  if (st == OKR_OK) p->tuned = true;
+  if (st == OKR_OK) {
+    p->tuned = true;
+    p->tune_cached = false;
+    TuneVal v{pick.grid, pick.upd, {}};
+    std::memcpy(v.ms, p->tune_ms, sizeof(v.ms));
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache.emplace_back(key, v);
+  }
   drop_graph(p);
   return st;
 }
 
 okr_status okr_plan_get_tuning(const okr_plan* p, int32_t* grid_per_cu, int32_t* update_arith,
-                               double* cand_ms) {
+                               double* cand_ms, int32_t* from_cache) {
   if (!p) return OKR_E_INVALID_ARG;
   if (grid_per_cu) *grid_per_cu = p->grid_per_cu;
   if (update_arith) *update_arith = p->upd;
   if (cand_ms)
     for (int i = 0; i < 8; ++i) cand_ms[i] = p->tune_ms[i];
+  if (from_cache) *from_cache = p->tune_cached ? 1 : 0;
   return OKR_OK;
 }
 

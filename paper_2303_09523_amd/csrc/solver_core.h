@@ -703,6 +703,86 @@ __device__ __forceinline__ void pipe_prefetch(Pipe& q, const SolveArgs& a, int k
   }
 }
 
+// ---- chunk staging ----
+// When a chunk's systems are consecutive columns of one row of one gap (the
+// common case in the size-sorted order, whose buckets keep system order), the
+// window rows of both slices they read are loaded once into LDS with
+// contiguous row loads, each system's values are then read from there, and
+// their estimates and variances are collected in LDS and written as one
+// contiguous row segment per target plane when the chunk is done.
+constexpr int kTileW = kChunk + 2 * kMaxRadius;
+struct ChunkStage {
+  float tile[2 * kMaxWin * kTileW];      // [slice][window row][column from x0 - r]
+  float est[kMaxUpsample - 1][kChunk];   // [target][system of the chunk]
+  float var[kMaxUpsample - 1][kChunk];
+};
+
+// Whether the chunk's nk systems (lane i holds system i) are one row run;
+// if so, loads the tile (coordinates clamped to the image: out-of-image
+// candidates are never kept, so those entries are never read) and returns the
+// run's gap, row and first column.
+__device__ __forceinline__ bool stage_chunk(const Pipe& q, const SolveArgs& a, int nk,
+                                            ChunkStage& cs, unsigned& gap, unsigned& y,
+                                            unsigned& x0) {
+  const int lane = threadIdx.x & 63;
+  const Geometry& geo = a.geo;
+  const unsigned sys0 = __builtin_amdgcn_readfirstlane(q.msys);
+  const unsigned plane = (unsigned)geo.plane, nx = (unsigned)geo.nx;
+  gap = sys0 / plane;
+  const unsigned pix = sys0 - gap * plane;
+  y = pix / nx;
+  x0 = pix - y * nx;
+  const bool mine = lane >= nk || q.msys == sys0 + (unsigned)lane;
+  if (!__all(mine) || x0 + (unsigned)nk > nx) return false;
+  const int r = geo.r, W = geo.W, cols = nk + 2 * r, per = W * cols;
+  for (int i = lane; i < 2 * per; i += 64) {
+    const int sl = i >= per;
+    const int rem = i - sl * per;
+    const int row = rem / cols, c = rem - row * cols;
+    int yy = (int)y + row - r, xx = (int)x0 + c - r;
+    yy = yy < 0 ? 0 : (yy >= geo.ny ? geo.ny - 1 : yy);
+    xx = xx < 0 ? 0 : (xx >= geo.nx ? geo.nx - 1 : xx);
+    cs.tile[(sl * kMaxWin + row) * kTileW + c] =
+        a.slices[(long long)(gap + sl * a.step) * geo.plane + (long long)yy * geo.nx + xx];
+  }
+  __builtin_amdgcn_wave_barrier();
+  return true;
+}
+
+// pipe_prefetch of system k of a staged chunk: the values come from the tile.
+__device__ __forceinline__ void pipe_prefetch_staged(Pipe& q, const ChunkStage& cs, int k, int d0,
+                                                     int d1, uint64_t below, int ncand) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lo = lane_u64(q.mlo, k), hi = lane_u64(q.mhi, k);
+  const int n0 = __popcll(lo);
+  q.pp0 = ((lo >> lane) & 1ull) ? __popcll(lo & below) : -1;
+  q.pp1 = (lane + 64 < ncand && ((hi >> lane) & 1ull)) ? n0 + __popcll(hi & below) : -1;
+  if (q.pp0 >= 0) {
+    const int c = (d0 >> 8) & 0xff;
+    q.pv0 = cs.tile[(((c >> 6) & 1) * kMaxWin + ((c >> 3) & 7)) * kTileW + k + (c & 7)];
+  }
+  if (q.pp1 >= 0) {
+    const int c = (d1 >> 8) & 0xff;
+    q.pv1 = cs.tile[(((c >> 6) & 1) * kMaxWin + ((c >> 3) & 7)) * kTileW + k + (c & 7)];
+  }
+}
+
+// The staged chunk's outputs, one contiguous row segment per target plane.
+__device__ __forceinline__ void flush_chunk(const SolveArgs& a, const ChunkStage& cs, int nk,
+                                            unsigned gap, unsigned y, unsigned x0) {
+  const int lane = threadIdx.x & 63;
+  const Geometry& geo = a.geo;
+  const int ntgt = geo.f - 1;
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < ntgt * nk; i += 64) {
+    const int t = i / nk, k = i - t * nk;
+    const long long o = ((long long)gap * geo.f + t + 1) * geo.plane + (long long)y * geo.nx + x0 + k;
+    a.volume[o] = cs.est[t][k];
+    if (a.variance) a.variance[o] = cs.var[t][k];
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Writes the system's points (n of them) in system order; the slots past the
 // last point get value 0 and the column offsets of a non-point.
 template <typename T>
@@ -775,7 +855,8 @@ __device__ __forceinline__ void flush_tally(const SolveArgs& a, const Tally& t) 
 template <typename T>
 __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsigned sys, int cnt,
                                               T est, T var, T mn, T mx, bool bad, Tally& tally,
-                                              bool route = false, uint8_t extra_flags = 0) {
+                                              bool route = false, uint8_t extra_flags = 0,
+                                              ChunkStage* cs = nullptr, int k = 0) {
   const int lane = threadIdx.x & 63;
   const Geometry& geo = a.geo;
   const int ntgt = geo.f - 1;
@@ -791,9 +872,14 @@ __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsi
       a.fallback[slot] = sys;
     }
   } else if (lane < ntgt) {
-    const long long o = ((long long)gap * geo.f + lane + 1) * geo.plane + pix;
-    a.volume[o] = (float)est;
-    if (a.variance) a.variance[o] = (float)var;
+    if (cs) {   // written with the rest of the staged chunk
+      cs->est[lane][k] = (float)est;
+      cs->var[lane][k] = (float)var;
+    } else {
+      const long long o = ((long long)gap * geo.f + lane + 1) * geo.plane + pix;
+      a.volume[o] = (float)est;
+      if (a.variance) a.variance[o] = (float)var;
+    }
   }
   if (lane == 0 && a.flags) {
     uint8_t fl = ((cnt & kFloorBit) ? kFlagFloor : 0) | extra_flags;

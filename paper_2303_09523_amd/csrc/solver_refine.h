@@ -21,16 +21,8 @@ namespace okr {
 namespace {
 
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ f32x4 mfma_k32(h8 a, h8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mfma_k32(b8 a, b8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
 __device__ __forceinline__ f32x4 mfma_k16(h4 a, h4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
@@ -39,8 +31,8 @@ __device__ __forceinline__ f32x4 mfma_k16(b4 a, b4 b, f32x4 c) {
 }
 
 // Storage of finished L tiles for the trailing updates: the tiles of block
-// columns 2m and 2m+1 of one block row are kept together, already in the
-// operand form of one K=32 MFMA (elements 0..3: column 2m, 4..7: column 2m+1).
+// columns 2m and 2m+1 of one block row are kept together (h = 0, 1), each as
+// the operand of the 16x16x16 (or, FP32, 16x16x4) MFMAs of its products.
 template <int UPD> struct PairStore;
 
 template <> struct PairStore<0> {
@@ -51,7 +43,7 @@ template <> struct PairStore<0> {
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-template <typename E, typename V4, typename V8> struct SplitPair {
+template <typename E, typename V4> struct SplitPair {
   typedef E V2 __attribute__((ext_vector_type(2)));
   V4 hi[2], lo[2];   // whole 4-element halves; concatenated at each use
   // hi = round(x), lo = round(x - hi), two elements per packed conversion
@@ -69,15 +61,9 @@ template <typename E, typename V4, typename V8> struct SplitPair {
     for (int v = 0; v < 4; ++v) x[v] = (float)hi[h][v] + (float)lo[h][v];
     return x;
   }
-  __device__ __forceinline__ V8 hi8() const {
-    return __builtin_shufflevector(hi[0], hi[1], 0, 1, 2, 3, 4, 5, 6, 7);
-  }
-  __device__ __forceinline__ V8 lo8() const {
-    return __builtin_shufflevector(lo[0], lo[1], 0, 1, 2, 3, 4, 5, 6, 7);
-  }
 };
-template <> struct PairStore<1> : SplitPair<_Float16, h4, h8> {};
-template <> struct PairStore<2> : SplitPair<__bf16, b4, b8> {};
+template <> struct PairStore<1> : SplitPair<_Float16, h4> {};
+template <> struct PairStore<2> : SplitPair<__bf16, b4> {};
 
 // c += Q P^T summed over both block columns of a pair.
 template <int UPD>

@@ -91,6 +91,14 @@ def test_autotune_keeps_results():
     # the launch shape only changes which wave takes which system
     assert torch.equal(v, v_ref) and torch.equal(w, w_ref)
     plan.close()
+    # a second plan with the same key takes the cached shape without timing
+    again = P.Plan(nx, ny, n, f, r, precision="fp32")
+    t2 = again.autotune(st, vario, et)
+    print("fp32 tuning again", t2, flush=True)
+    assert t2["from_cache"]
+    assert (t2["grid_per_cu"], t2["update_arith"]) == (t["grid_per_cu"], t["update_arith"])
+    assert t2["candidate_ms"] == t["candidate_ms"]
+    again.close()
     # mixed: the tuned update arithmetic still meets the refined bar
     vo, _, _ = O.krige_volume(s, e, f, r, vario)
     plan = P.Plan(nx, ny, n, f, r, precision="mixed_fp16")
