@@ -77,8 +77,12 @@ typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 
 
 /* BATCHED: selection, size bucketing and one persistent factorisation launch,
  * one Cholesky per (column, gap) shared by its f-1 targets.
- * PLAIN_PER_VOXEL: one bordered LU (partial pivoting) per kriged voxel with
- * direct covariance evaluation; the comparison kernel.
+ * PLAIN_PER_VOXEL: the comparison kernel: one wavefront per kriged voxel,
+ * nothing shared between voxels: its own selection, covariances from the FP64
+ * tables rounded to FP32, Cholesky of C in LDS (FP32), the bordered solution
+ * from C^{-1} 1 and C^{-1} c0, and with refine_max = 1 one step of iterative
+ * refinement with the FP64 residual of the bordered system; estimate and
+ * variance summed in FP64.
  * PATTERN_CACHE: BATCHED, except that the systems keeping the whole window
  * (the same matrix for all of them, by translation invariance) take weights
  * and variances computed once per launch in FP64 and applied as FP64 dot

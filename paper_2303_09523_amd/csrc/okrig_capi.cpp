@@ -18,7 +18,6 @@
 #include "okrig_internal.h"
 
 namespace okr {
-size_t plain_shared_bytes(const Geometry& g);
 hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, int ngaps,
                               const SelectRule& rule, uint64_t* bits, uint8_t* count,
                               DevCounters* c, hipStream_t s);
@@ -596,7 +595,8 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   if (p->prob.algo == OKR_ALGO_PLAIN_PER_VOXEL) {
     PhaseTimer t(p, OKR_PHASE_PLAIN);
     OKR_HIP(p, okr::launch_plain(d_slices, d_edge, d_volume, d_variance, g, p->rule,
-                                 vario_of(vario), strm));
+                                 vario_of(vario), tables_of(p), p->prob.refine_max > 0 ? 1 : 0,
+                                 p->num_cu, strm));
     return OKR_OK;
   }
   {

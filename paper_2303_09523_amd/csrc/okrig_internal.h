@@ -140,7 +140,8 @@ hipError_t launch_select_step(const uint8_t* edge, const Geometry& g, int step, 
 
 // ---- launchers (kernels_plain.hip) ----
 hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume, float* variance,
-                        const Geometry& g, const SelectRule& rule, const Vario& v, hipStream_t s);
+                        const Geometry& g, const SelectRule& rule, const Vario& v, TableSet tab,
+                        int refine, int num_cu, hipStream_t s);
 
 // ---- marching cubes (mcubes_table.cpp, kernels_mcubes.hip) ----
 constexpr int kMcMaxTri = 5;     // triangles of one cube configuration, at most

@@ -97,11 +97,15 @@ def test_batched_vs_oracle(case, precision, oracle_cache):
     assert st["bucket"] == hist.tolist()
 
 
+@pytest.mark.parametrize("refine_max", [1, 0])
 @pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
-def test_plain_vs_oracle(case, oracle_cache):
+def test_plain_vs_oracle(case, refine_max, oracle_cache):
+    """The per-voxel comparison kernel: with its FP64-residual refinement step
+    per voxel <= 1e-5, without it the FP32 bar."""
     name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
     s, e, vol_o, var_o, _ = _oracle(oracle_cache, case)
-    vol, var, _, _ = run_gpu(s, e, f, r, (model, nug, sill, rng_), algo="plain")
+    vol, var, _, _ = run_gpu(s, e, f, r, (model, nug, sill, rng_), algo="plain",
+                             min_points=min(4, 2 * (2 * r + 1) ** 2), refine_max=refine_max)
     np.testing.assert_array_equal(vol[::f], s)
     kz = np.ones(vol.shape[0], bool)
     kz[::f] = False
@@ -109,9 +113,9 @@ def test_plain_vs_oracle(case, oracle_cache):
     ee = rel_err_est(vol[kz], vol_o[kz], zmax)
     ev = rel_err_var(var[kz], var_o[kz], sill)
     nw = np.abs(vol[kz].astype(np.float64) - vol_o[kz]).max() / np.abs(vol_o[kz]).max()
-    print(f"case {name} plain: max est err {ee.max():.3e} var err {ev.max():.3e} normwise {nw:.3e}",
-          flush=True)
-    assert ee.max() <= TOL["fp32"]
+    print(f"case {name} plain refine_max={refine_max}: max est err {ee.max():.3e} "
+          f"var err {ev.max():.3e} normwise {nw:.3e}", flush=True)
+    assert ee.max() <= (1e-5 if refine_max else TOL["fp32"])
     assert ev.max() <= 1e-5
     assert nw <= NORMWISE_FP32
 
