@@ -26,10 +26,13 @@ written readings, not this code):
 * Shearlet system. The system of Appendix B, psi_{a,s,t}(x) =
   a^{-3/4} psi(A_a^{-1} S_s^{-1} (x - t)), A_a = diag(a, sqrt a),
   S_s = [[1, -s], [0, 1]], with a separable mother shearlet
-  psi(u1, u2) = psi1(u1) phi(u2): psi1(u) = -(u / s1^2) exp(-u^2 / (2 s1^2))
-  (a first-derivative-of-Gaussian wavelet, s1 = 4) and
-  phi(u) = exp(-u^2 / (2 sp^2)) (sp = 3), at the scale a = 1/4, sampled at
-  the integer offsets |d1|, |d2| <= 4 (9 x 9 taps, t = the pixel). Image axes:
+  psi(u1, u2) = psi1(u1) phi(u2) of compact support: the odd wavelet
+  psi1(u) = -u (1 - (u/10)^2)^2 for |u| < 10 (0 elsewhere) and the window
+  phi(u) = (1 - (u/10)^2)^2 for |u| < 10, at the scale a = 1/4 (so
+  a^{-3/4} = 2 sqrt 2 and sqrt a = 1/2), sampled at the integer offsets
+  |d1|, |d2| <= 4 (9 x 9 taps, t = the pixel). Every tap is a polynomial in
+  exact binary fractions times 2 sqrt 2, so two correctly rounded evaluations
+  in the same operation order agree bit for bit. Image axes:
   x1 = y (columns), x2 = z (rows). Two cones: horizontal,
   psi1((x1 + s x2) / a) phi(x2 / sqrt a), s in {-1, -1/2, 0, 1/2}; vertical
   (x1 and x2 exchanged), psi1((x2 + s x1) / a) phi(x1 / sqrt a),
@@ -74,7 +77,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-S1, SP, SCALE_A, RADIUS = 4.0, 3.0, 0.25, 4
+SUPPORT, RADIUS = 10.0, 4   # support of psi1 and phi; taps |d| <= RADIUS
 # (cone, shear): cone 0 horizontal, 1 vertical
 SHEARS = [(0, -1.0), (0, -0.5), (0, 0.0), (0, 0.5), (1, 1.0), (1, 0.5), (1, 0.0), (1, -0.5)]
 K = len(SHEARS)
@@ -90,25 +93,36 @@ def normal_angle(k: int) -> float:
     return math.degrees(math.atan(s)) if cone == 0 else 90.0 - math.degrees(math.atan(s))
 
 
+def _psi1(u: float) -> float:
+    if abs(u) >= SUPPORT:
+        return 0.0
+    q = 1.0 - (u / SUPPORT) * (u / SUPPORT)
+    return -u * (q * q)
+
+
+def _phi(u: float) -> float:
+    if abs(u) >= SUPPORT:
+        return 0.0
+    q = 1.0 - (u / SUPPORT) * (u / SUPPORT)
+    return q * q
+
+
 def shearlet_filters() -> np.ndarray:
-    """psi_k(d) for k < K, taps [k][d2 + R][d1 + R] (Appendix B, readings above)."""
+    """psi_k(d) for k < K, taps [k][d2 + R][d1 + R] (Appendix B, readings above):
+    a^{-3/4} psi1(u1 / a) phi(u2 / sqrt a) with (u1, u2) = S_s^{-1} d for the
+    horizontal cone and the axes exchanged for the vertical one."""
     R = RADIUS
-    d = np.arange(-R, R + 1, dtype=np.float64)
-    d2, d1 = np.meshgrid(d, d, indexing="ij")
-
-    def psi1(u):
-        return -(u / S1 ** 2) * np.exp(-u * u / (2 * S1 ** 2))
-
-    def phi(u):
-        return np.exp(-u * u / (2 * SP ** 2))
-
-    a, ra = SCALE_A, math.sqrt(SCALE_A)
+    norm = 2.0 * math.sqrt(2.0)        # a^{-3/4} at a = 1/4
     out = np.empty((K, 2 * R + 1, 2 * R + 1))
     for k, (cone, s) in enumerate(SHEARS):
-        if cone == 0:
-            out[k] = a ** -0.75 * psi1((d1 + s * d2) / a) * phi(d2 / ra)
-        else:
-            out[k] = a ** -0.75 * psi1((d2 + s * d1) / a) * phi(d1 / ra)
+        for i2 in range(2 * R + 1):
+            for i1 in range(2 * R + 1):
+                d1, d2 = float(i1 - R), float(i2 - R)
+                if cone == 0:
+                    u, v = d1 + s * d2, d2
+                else:
+                    u, v = d2 + s * d1, d1
+                out[k, i2, i1] = norm * (_psi1(u * 4.0) * _phi(v * 2.0))
     return out
 
 

@@ -53,9 +53,9 @@ def test_step5_sides_match_the_example():
 def test_filters_have_zero_mean():
     taps = E.shearlet_filters()
     assert taps.shape == (E.K, 2 * E.RADIUS + 1, 2 * E.RADIUS + 1)
-    assert np.abs(taps.sum(axis=(1, 2))).max() <= 1e-14
+    assert np.abs(taps.sum(axis=(1, 2))).max() <= 1e-13 * np.abs(taps).max()
     sh = E.shearlet_coefficients(np.full((20, 23), 3.7))
-    assert np.abs(sh).max() <= 1e-13
+    assert np.abs(sh).max() <= 1e-12
 
 
 def test_cones_are_transposes():
@@ -126,11 +126,15 @@ def test_postpass_on_a_noisy_disc_is_deterministic_and_local():
     x2, x1 = np.mgrid[0:H, 0:W]
     img = (((x1 - 21.5) ** 2 + (x2 - 19.2) ** 2) < 12.3 ** 2).astype(np.float32) * 0.8
     img += rng.normal(0, 0.05, size=img.shape).astype(np.float32)
-    out, emap, tmap = E.edge_postpass_image(img, 0.5)
-    out2, emap2, tmap2 = E.edge_postpass_image(img, 0.5)
+    step = np.zeros((30, 30))
+    step[:, 15:] = 1.0
+    gain = np.abs(E.shearlet_coefficients(step)).max()   # response to a unit step
+    tau = 0.4 * 0.8 * gain
+    out, emap, tmap = E.edge_postpass_image(img, tau)
+    out2, emap2, tmap2 = E.edge_postpass_image(img, tau)
     assert np.array_equal(out, out2) and np.array_equal(emap, emap2)
     r = np.hypot(x1 - 21.5, x2 - 19.2)
-    edge0, _, _ = E.edges_and_orientation(img, 0.5)
+    edge0, _, _ = E.edges_and_orientation(img, tau)
     assert edge0.sum() > 40
     assert (np.abs(r[edge0 > 0] - 12.3) <= 2.5).all()
     changed = out != img
