@@ -162,12 +162,13 @@ typedef struct {
   int64_t n_fp64_fallback;    /* systems re-solved in FP64 */
   int64_t n_nonpositive_pivot;/* systems with a non-positive pivot in the first pass */
   double  max_kappa_est;      /* largest pivot-ratio condition estimate */
-  double  phase_ms[10];       /* with profiling on: summed device time per phase since the
+  double  phase_ms[11];       /* with profiling on: summed device time per phase since the
                                  last okr_stats_get: 0 placement, 1 tables, 2 selection,
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
                                  6 plain per-voxel kernel, 7 leave-one-slice-out,
-                                 8 full-window pattern weights + application, 9 unused */
-  int64_t phase_calls[10];    /* launches timed per phase */
+                                 8 full-window pattern weights + application,
+                                 9 marching cubes, 10 edge post-pass */
+  int64_t phase_calls[11];    /* launches timed per phase */
   int64_t n_not_converged;    /* systems whose FP64 re-solve also met a non-positive pivot */
   int64_t n_refine_unconverged; /* systems whose correction left refine_tol unmet (each
                                    re-solved in FP64, so also in n_fp64_fallback) */
@@ -186,7 +187,8 @@ typedef struct {
 #define OKR_PHASE_LOSO 7
 #define OKR_PHASE_PATTERN 8
 #define OKR_PHASE_MESH 9
-#define OKR_NUM_PHASES 10
+#define OKR_PHASE_EDGE 10
+#define OKR_NUM_PHASES 11
 
 /* Create a plan for one problem shape. `hip_stream` is a hipStream_t (NULL =
  * the default stream). Validates every field (OKR_E_INVALID_ARG / SHAPE /
@@ -280,6 +282,54 @@ okr_status okr_krige_points(okr_plan* plan, const okr_variogram* vario, int64_t 
  * 64 cubes of a row) is allocated by the first call. */
 okr_status okr_marching_cubes(okr_plan* plan, const float* d_volume, float iso, float* d_tris,
                               int64_t* d_cube, int64_t max_tris, int64_t* n_tris);
+
+/* The paper's edge post-pass (Section 4.1.2, Algorithm 2; shearlets of
+ * Appendix B) on a float32 volume of the plan's output shape [nz][ny][nx],
+ * nz = (nslices-1)*upsample+1, image by image along the YZ plane
+ * (I_x(z, y) = V[z][y][x]; image rows z, columns y):
+ *   1. FP64 coefficients SH_k(p) = sum_d psi_k(d) I(p + d) of 8 orientations
+ *      (the filters okr_edge_filters returns; border replicated), summed with
+ *      d2 (rows) outer and d1 (columns) inner, each product rounded before it
+ *      is added; M = max_k |SH_k|, theta = the first k attaining it;
+ *   2. p is an edge pixel iff M(p) >= tau and neither neighbour p +- n
+ *      (n: the normal of theta rounded to 45 degrees, okr_edge_filters'
+ *      normals; out-of-image neighbours do not count) has a larger M;
+ *   3. chains: pixels in row-major order each start a chain at an edge pixel
+ *      not yet visited; a chain moves to the first unvisited edge pixel among
+ *      the 8 neighbours of its last pixel, searched clockwise (y right, z
+ *      down: E, SE, S, SW, W, NW, N, NE) from three steps counter-clockwise of
+ *      its last move (from E at the start); each full group of 16 consecutive
+ *      chain pixels is a window;
+ *   4. a window whose orientation changes at least 4 times between
+ *      consecutive pixels is noise: its representative orientation is the
+ *      most frequent one (ties: the first seen in the window); walking the
+ *      window from its first pixel, each interior pixel with another
+ *      orientation is replaced by the previous kept or new pixel plus the
+ *      tangent t (the representative's rounded normal turned by 90 degrees,
+ *      pointing from the first toward the last pixel; a replacement outside
+ *      the image keeps the pixel);
+ *   5. around each new edge pixel the 3 neighbours on each side of t (sign of
+ *      t x d) that lie in the image take their median; windows apply in
+ *      chain order, so later medians see earlier ones.
+ * Arguments:
+ *   d_volume  float32 [nz][ny][nx] input, finite (required)
+ *   d_out     float32 [nz][ny][nx] the adjusted volume (required; may equal
+ *             d_volume for an in-place pass, otherwise it must not overlap it)
+ *   tau       edge threshold on M (finite)
+ *   d_edge    uint8 [nz][ny][nx] edge map after the pass, 1 = edge (nullable)
+ *   d_orient  uint8 [nz][ny][nx] orientation 0..7 after the pass (nullable)
+ *   d_mag     float64 [nz][ny][nx] M of step 1 (nullable)
+ * The workspace (9 bytes per voxel and one bit per pixel) is allocated by the
+ * first call. Stream-ordered; the result does not depend on the launch
+ * shape. Non-finite voxels give unspecified edges (no error is raised). */
+okr_status okr_edge_postpass(okr_plan* plan, const float* d_volume, float* d_out, double tau,
+                             uint8_t* d_edge, uint8_t* d_orient, double* d_mag);
+
+/* The edge post-pass's filters and rounded normals as the library uses them
+ * (host only, no device work): taps[k][d2 + 4][d1 + 4] for k < 8 (648
+ * doubles) and normals[2k], normals[2k+1] = (d1, d2) of orientation k (16
+ * int32). Either pointer may be NULL. */
+okr_status okr_edge_filters(double* taps, int32_t* normals);
 
 /* Counters of the last execute / loso call; synchronises the plan's stream and
  * returns any latched device-side error (e.g. OKR_E_NONFINITE). */

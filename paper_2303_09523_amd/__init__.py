@@ -40,6 +40,18 @@ def _as_vario(v):
     return _vario(v.model, v.nugget, v.sill, v.range)
 
 
+def edge_filters():
+    """The edge post-pass's filters as the library evaluates them (host only):
+    (taps float64 [8][9][9] indexed [k][d2 + 4][d1 + 4], normals int32 [8][2]
+    as (d1, d2))."""
+    import numpy as np
+    taps = np.zeros((8, 9, 9), dtype=np.float64)
+    normals = np.zeros((8, 2), dtype=np.int32)
+    _lib.check(load().okr_edge_filters(taps.ctypes.data_as(C.c_void_p),
+                                       normals.ctypes.data_as(C.c_void_p)), None)
+    return taps, normals
+
+
 class Plan:
     """One problem shape: workspace and launch state owned by the library."""
 
@@ -180,6 +192,30 @@ class Plan:
                                               _ptr(ids), tris.shape[0], C.byref(n)), self._h)
         T = min(n.value, tris.shape[0])
         return tris[:T], (ids[:T] if ids is not None else None)
+
+    def edge_postpass(self, volume, tau, out=None, edge=None, orient=None, mag=None):
+        """The edge post-pass (okr_edge_postpass) on a float32 volume of the
+        plan's output shape: returns (out, edge, orient) CUDA tensors, the
+        adjusted volume (float32; pass out=volume for an in-place pass), the
+        edge map and the orientation map (uint8) after the pass; with a
+        float64 tensor `mag` the coefficient magnitude M is written too."""
+        torch = _torch()
+        shape = self.out_shape()
+        self._check_in(volume, torch.float32, shape, "volume")
+        if out is None:
+            out = torch.empty_like(volume)
+        if edge is None:
+            edge = torch.empty(shape, dtype=torch.uint8, device=volume.device)
+        if orient is None:
+            orient = torch.empty(shape, dtype=torch.uint8, device=volume.device)
+        self._check_in(out, torch.float32, shape, "out")
+        self._check_in(edge, torch.uint8, shape, "edge")
+        self._check_in(orient, torch.uint8, shape, "orient")
+        if mag is not None:
+            self._check_in(mag, torch.float64, shape, "mag")
+        _lib.check(load().okr_edge_postpass(self._h, _ptr(volume), _ptr(out), C.c_double(tau),
+                                            _ptr(edge), _ptr(orient), _ptr(mag)), self._h)
+        return out, edge, orient
 
     def select(self, edge=None):
         """Kept-candidate bitmasks [(n-1)*ny*nx][2] (int64 view of uint64) and counts."""

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "OKR_OK", 1: "OKR_E_INVALID_ARG", 2: "OKR_E_SHAPE", 3: "OKR_E
                 7: "OKR_E_NOT_CONVERGED", 8: "OKR_E_CAPACITY"}
 MODELS = {"spherical": 0, "exponential": 1, "gaussian": 2}
 PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso", "pattern",
-          "mesh"]
+          "mesh", "edge"]
 PRECISIONS = {"fp32": 0, "mixed_fp16": 1, "mixed_bf16": 2, "fp64": 3}
 ALGOS = {"batched": 0, "plain": 1, "pattern": 2}
 
@@ -25,7 +25,8 @@ EXPORTED = ["okr_plan_create", "okr_execute", "okr_select", "okr_loso_forward",
             "okr_loso_backward", "okr_stats_get", "okr_plan_destroy", "okr_status_string",
             "okr_plan_last_error", "okr_version", "okr_abi_sizes", "okr_plan_set_profiling",
             "okr_plan_set_graph", "okr_plan_autotune", "okr_plan_get_tuning",
-            "okr_krige_points", "okr_marching_cubes", "okr_execute_noalloc"]
+            "okr_krige_points", "okr_marching_cubes", "okr_execute_noalloc",
+            "okr_edge_postpass", "okr_edge_filters"]
 
 
 class Variogram(C.Structure):
@@ -44,8 +45,8 @@ class Stats(C.Structure):
     _fields_ = [("n_systems", C.c_int64), ("n_kriged", C.c_int64), ("bucket", C.c_int64 * 128),
                 ("n_floor_filled", C.c_int64), ("n_refined", C.c_int64),
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
-                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 10),
-                ("phase_calls", C.c_int64 * 10), ("n_not_converged", C.c_int64),
+                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 11),
+                ("phase_calls", C.c_int64 * 11), ("n_not_converged", C.c_int64),
                 ("n_refine_unconverged", C.c_int64), ("kappa_window", C.c_double)]
 
 
@@ -91,6 +92,8 @@ def load():
                                             P(C.c_int32)]),
         "okr_execute_noalloc": (C.c_int32, [P(Problem), VP, P(Variogram), VP, VP, VP, VP, VP,
                                             VP]),
+        "okr_edge_postpass": (C.c_int32, [VP, VP, VP, C.c_double, VP, VP, VP]),
+        "okr_edge_filters": (C.c_int32, [VP, VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

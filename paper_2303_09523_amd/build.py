@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libokrig.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["okrig_capi.cpp", "kernels_select.hip", "kernels_solve.hip", "kernels_mixed.hip",
            "kernels_plain.hip", "kernels_adjoint.hip", "kernels_points.hip",
-           "kernels_mcubes.hip", "mcubes_table.cpp"]
+           "kernels_mcubes.hip", "mcubes_table.cpp", "kernels_edge.hip"]
 ARCH = "gfx950"
 # Packed FP32 instructions are disabled for every device compile.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/okrig.h"
+#include "edge_filters.h"
 #include "okrig_internal.h"
 
 namespace okr {
@@ -45,6 +46,10 @@ struct okr_plan {
   okr::McTable* mc_tab = nullptr;       // marching cubes (first call): case table,
   uint32_t* mc_cnt = nullptr;           // triangles per (row, strip), then offsets,
   unsigned long long* mc_tile = nullptr;  // tile offsets and the total
+  double* edge_mag = nullptr;           // edge post-pass (first call): M per voxel,
+  uint8_t* edge_theta = nullptr;        // orientation per voxel,
+  uint32_t* edge_bits = nullptr;        // per-image edge bitmaps
+  int edge_lds_max = -1;                // largest dynamic LDS of one workgroup (bytes)
   bool loso_ready = false;
   okr_variogram loso_vario{};
   const float* loso_slices = nullptr;
@@ -248,6 +253,9 @@ void free_plan(okr_plan* p) {
   hipFree(p->mc_tab);
   hipFree(p->mc_cnt);
   hipFree(p->mc_tile);
+  hipFree(p->edge_mag);
+  hipFree(p->edge_theta);
+  hipFree(p->edge_bits);
   delete p;
 }
 
@@ -918,6 +926,111 @@ okr_status okr_marching_cubes(okr_plan* p, const float* d_volume, float iso, flo
     return fail(p, OKR_E_CAPACITY,
                 "marching cubes: " + std::to_string(total) + " triangles, buffer holds " +
                     std::to_string(max_tris));
+  return OKR_OK;
+}
+
+namespace {
+
+// Rounded normals (d1, d2) of the eight orientations: the normal angle
+// (atan s from the x1 axis for the horizontal cone, 90 degrees minus atan s
+// for the vertical one) to the nearest multiple of 45 degrees.
+void edge_normals(int n1[8], int n2[8]) {
+  static const int off1[4] = {1, 1, 0, -1}, off2[4] = {0, 1, 1, 1};
+  for (int k = 0; k < okr::edge::kOrient; ++k) {
+    const double deg = std::atan(okr::edge::kShears[k].s) * (180.0 / M_PI);
+    const double ang = okr::edge::kShears[k].cone == 0 ? deg : 90.0 - deg;
+    const int q = (((int)std::nearbyint(ang / 45.0)) % 4 + 4) % 4;
+    n1[k] = off1[q];
+    n2[k] = off2[q];
+  }
+}
+
+}  // namespace
+
+okr_status okr_edge_filters(double* taps, int32_t* normals) {
+  if (taps)
+    std::memcpy(taps, &okr::edge::kTapTable, sizeof(okr::edge::kTapTable));
+  if (normals) {
+    int n1[8], n2[8];
+    edge_normals(n1, n2);
+    for (int k = 0; k < 8; ++k) {
+      normals[2 * k] = n1[k];
+      normals[2 * k + 1] = n2[k];
+    }
+  }
+  return OKR_OK;
+}
+
+okr_status okr_edge_postpass(okr_plan* p, const float* d_volume, float* d_out, double tau,
+                             uint8_t* d_edge, uint8_t* d_orient, double* d_mag) {
+  if (!p) return OKR_E_INVALID_ARG;
+  if (!d_volume || !d_out) return fail(p, OKR_E_INVALID_ARG, "volume and out are required");
+  if (!std::isfinite(tau)) return fail(p, OKR_E_INVALID_ARG, "tau must be finite");
+  if (std::sqrt(2.0) != okr::edge::kSqrt2)
+    return fail(p, OKR_E_UNSUPPORTED, "host sqrt(2) differs from the filters' constant");
+  const okr::Geometry& g = p->geo;
+  const long long nz = (long long)(g.nslices - 1) * g.f + 1, ny = g.ny, nx = g.nx;
+  const long long vox = nz * ny * nx;
+  const int wr = okr::edge_words_per_row((int)ny);
+  const long long words = (nz + 2) * wr;
+  if (nz < 1 || vox <= 0) return OKR_OK;
+  if (nz + 2 > 0x7fffffffLL || words > 0x7fffffffLL || (words + 3) / 4 > 0x7fffffffLL)
+    return fail(p, OKR_E_SHAPE, "volume too large for the edge post-pass");
+  const char* vb = reinterpret_cast<const char*>(d_volume);
+  const char* ob = reinterpret_cast<const char*>(d_out);
+  const long long bytes = vox * (long long)sizeof(float);
+  if (vb != ob && vb < ob + bytes && ob < vb + bytes)
+    return fail(p, OKR_E_INVALID_ARG, "out overlaps volume without being equal to it");
+  if (!p->edge_mag) {
+    if (hipMalloc(&p->edge_mag, sizeof(double) * vox) != hipSuccess ||
+        hipMalloc(&p->edge_theta, vox) != hipSuccess ||
+        hipMalloc(&p->edge_bits, sizeof(uint32_t) * words * nx) != hipSuccess) {
+      (void)hipGetLastError();
+      hipFree(p->edge_mag);
+      hipFree(p->edge_theta);
+      hipFree(p->edge_bits);
+      p->edge_mag = nullptr;
+      p->edge_theta = nullptr;
+      p->edge_bits = nullptr;
+      return fail(p, OKR_E_OOM, "edge post-pass workspace");
+    }
+  }
+  if (p->edge_lds_max < 0) {
+    int v = 0;
+    OKR_HIP(p, hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+    p->edge_lds_max = v;
+  }
+  okr::EdgeArgs a{};
+  a.volume = d_volume;
+  a.out = d_out;
+  a.mag = d_mag ? d_mag : p->edge_mag;
+  a.theta = p->edge_theta;
+  a.bits = p->edge_bits;
+  a.edge_out = d_edge;
+  a.orient_out = d_orient;
+  a.tau = tau;
+  a.nz = (int)nz;
+  a.ny = (int)ny;
+  a.nx = (int)nx;
+  a.wr = wr;
+  int n1[8], n2[8];
+  edge_normals(n1, n2);
+  for (int k = 0; k < 8; ++k) {
+    a.n1 |= (uint32_t)(n1[k] + 1) << (4 * k);
+    a.n2 |= (uint32_t)(n2[k] + 1) << (4 * k);
+  }
+  // the bitmap of one image in LDS when it fits in 64 KB with the window
+  // record (and below the device's limit), else traced in place in global
+  // memory
+  const size_t lds = sizeof(uint32_t) * (size_t)words;
+  const size_t lds_cap = std::min<size_t>((size_t)p->edge_lds_max, 65536);
+  const size_t lds_use = lds + 512 <= lds_cap ? lds : 0;
+  PhaseTimer t(p, OKR_PHASE_EDGE);
+  if (d_out != d_volume)
+    OKR_HIP(p, hipMemcpyAsync(d_out, d_volume, bytes, hipMemcpyDeviceToDevice, p->stream));
+  OKR_HIP(p, okr::launch_edge_shear(a, p->stream));
+  OKR_HIP(p, okr::launch_edge_nms(a, p->stream));
+  OKR_HIP(p, okr::launch_edge_trace(a, lds_use, p->stream));
   return OKR_OK;
 }
 

@@ -46,3 +46,14 @@ def test_gaussian_field_covariance():
         emp = (f[:, :, lag:] * f[:, :, :-lag]).mean()
         model = 0.78 * np.exp(-3.0 * lag / 5.0)
         assert emp == pytest.approx(model, rel=0.15, abs=0.02)
+
+
+def test_postpass_volume_deterministic():
+    w = W.workload("plain_8x64")
+    a = W.postpass_volume(w)
+    b = W.postpass_volume(w)
+    assert a.dtype == np.float32 and a.shape == (w.out_slices, 64, 64)
+    np.testing.assert_array_equal(a, b)
+    # planes z = s*f carry the phantom of the known slices up to the noise
+    clean = W.phantom_at(w, [0.0])
+    assert np.abs(a[0] - clean[0]).max() < 8 * w.noise

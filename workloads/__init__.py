@@ -25,7 +25,7 @@ import numpy as np
 
 __all__ = [
     "Variogram", "Workload", "WORKLOADS", "workload", "phantom", "phantom_at",
-    "sobel_edges", "gaussian_field", "make_inputs",
+    "sobel_edges", "gaussian_field", "make_inputs", "EDGE_TAU", "postpass_volume",
 ]
 
 
@@ -151,6 +151,22 @@ def phantom_at(w: Workload, zs, seed: Optional[int] = None) -> np.ndarray:
     zmax = float(w.upsample * (w.nslices - 1))
     objs = _draw_objects(rng, w.m, zmax, w.n_ellipsoids, w.n_shells)
     return _render(objs, w.m, np.asarray(zs, dtype=np.float64))
+
+
+# Edge threshold of the post-pass workloads: with the post-pass filters about
+# 3% of the pixels of a noisy phantom volume are edges (Section 4.1.2 leaves
+# the threshold open).
+EDGE_TAU = 4.0
+
+
+def postpass_volume(w: Workload, seed: Optional[int] = None) -> np.ndarray:
+    """Input of the edge post-pass in place of a reconstructed volume: the
+    phantom at every output plane z = 0 .. (nslices-1)*f with iid Gaussian
+    noise of the workload's level, float32 [out_slices][m][m]."""
+    base = w.seed if seed is None else seed
+    vol = phantom_at(w, np.arange(w.out_slices, dtype=np.float64), seed=base)
+    rng = np.random.default_rng(base + 7919)
+    return (vol + rng.normal(0.0, w.noise, size=vol.shape)).astype(np.float32)
 
 
 def sobel_edges(slices: np.ndarray, threshold: float = 0.5) -> np.ndarray:
