@@ -25,6 +25,8 @@ Prints ONE JSON line. Extra keys:
   accuracy          the headline result vs the oracle on that sample
   batched_variants  the other operating points (read-out only, FP64, FP32),
                     each with its accuracy on the same sample
+  next_rows         pattern_cache (full-window weight cache), marching_cubes and
+                    edge_postpass, below
   plain_fp32        the per-voxel comparison kernel
   other_configs     the small and the edge-preserved workloads: batched FP32,
                     refined mixed and the plain per-voxel kernel
@@ -32,6 +34,9 @@ Prints ONE JSON line. Extra keys:
                     mode, with routing counts and per-voxel errors
   loso              leave-one-slice-out loss + adjoint gradient timing on the
                     16 x 128^2 field workload
+  marching_cubes    the iso-surface of the reconstructed volume
+  edge_postpass     the paper's edge post-pass on the reconstructed volume:
+                    per-kernel times and the shearlet kernel's FP64 roofline
 """
 from __future__ import annotations
 
@@ -196,11 +201,84 @@ def cpu_baseline(w, s, e, target_s: float, seed: int = 12345):
             "time_reduction_vs_one_worker": 1.0 - one_value / value}, (idx, est, var)
 
 
+def edge_cpu_baseline(vol, tau: float, target_s: float):
+    """The edge post-pass oracle on whole YZ images of the volume (each image
+    is independent), in this process, until about target_s seconds."""
+    from oracle import edgepass as EP
+    nz, ny, nx = vol.shape
+    order = [(i * 97) % nx for i in range(nx)]
+    done, t0 = 0, time.perf_counter()
+    for x in order:
+        EP.edge_postpass_image(vol[:, :, x], tau)
+        done += 1
+        if time.perf_counter() - t0 >= target_s:
+            break
+    wall = time.perf_counter() - t0
+    return {"value": done * nz * ny / wall, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} whole YZ images ({nz}x{ny}) of the reconstructed volume, "
+                      f"FP64 NumPy + Python loops, one process, {wall:.1f} s"}
+
+
+def edge_postpass_record(w, vol, args, reps: int = 5):
+    """The paper's edge post-pass on the reconstructed volume: per-kernel
+    times from the library's HIP events, the shearlet kernel's FP64 roofline
+    and, unless --no-cpu, the oracle on whole sampled images."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2303_09523_amd as P
+    pe = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
+                refine_max=args.refine_max)
+    eout = torch.empty_like(vol)
+    emap = torch.empty(vol.shape, dtype=torch.uint8, device=vol.device)
+    omap = torch.empty_like(emap)
+    pe.edge_postpass(vol, W.EDGE_TAU, out=eout, edge=emap, orient=omap)
+    pe.set_profiling(True)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(reps):
+        pe.edge_postpass(vol, W.EDGE_TAU, out=eout, edge=emap, orient=omap)
+    torch.cuda.synchronize()
+    e_wall = (time.perf_counter() - e0) / reps * 1e3
+    se = pe.stats()
+    pe.close()
+    eph = {k: se["phase_ms"][k] / max(1, se["phase_calls"][k])
+           for k in ("edge_shear", "edge_thin", "edge_trace")}
+    e_ms = sum(eph.values())
+    nvox = int(vol.numel())
+    # one product and one sum per nonzero tap of the eight filters
+    edge_fpv = 2 * int(np.count_nonzero(P.edge_filters()[0]))
+    sflops = edge_fpv * nvox
+    rec = {
+        "value": nvox / (e_ms * 1e-3), "unit": "voxels/s", "ms": round(e_ms, 4),
+        "wall_ms": round(e_wall, 4), "voxels": nvox, "tau": W.EDGE_TAU,
+        "edge_fraction": round(float(emap.float().mean().item()), 5),
+        "voxels_changed": int((eout != vol).sum().item()),
+        "phase_ms": {k: round(v, 4) for k, v in eph.items()},
+        "timing": "library HIP events around each of the three launches",
+        "roofline_shear": {
+            "bound": "alu", "achieved": round(sflops / (eph["edge_shear"] * 1e-3) / 1e12, 3),
+            "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+            "frac": round(sflops / (eph["edge_shear"] * 1e-3) / 1e12 / PEAKS["fp64_tflops"], 4),
+            "flops_per_voxel": edge_fpv,
+            # HBM bytes of one launch (committed counter summary, same sources)
+            "traffic": _counter_summary(f"traffic_edge_shear_{w.name}.txt", EDGE_TRAFFIC_SOURCES,
+                                        "shear_hbm_bytes_per_call"),
+            "algorithmic_bytes": 14 * nvox}}
+    if not args.no_cpu:
+        rec["cpu_baseline"] = edge_cpu_baseline(vol.cpu().numpy(), W.EDGE_TAU,
+                                                min(10.0, args.cpu_seconds))
+    del eout, emap, omap
+    print(f"# edge post-pass: {e_ms:.3f} ms ({eph})", file=sys.stderr, flush=True)
+    return rec
+
+
 TRAFFIC_SOURCES = ["okrig_internal.h", "solver_core.h", "solver_refine.h", "kernels_solve.hip",
                    "kernels_mixed.hip"]
 
 
 MESH_TRAFFIC_SOURCES = ["okrig_internal.h", "kernels_mcubes.hip"]
+EDGE_TRAFFIC_SOURCES = ["okrig_internal.h", "edge_filters.h", "kernels_edge.hip"]
 
 
 def _source_hash(names) -> str:
@@ -267,6 +345,7 @@ def class_counts(bucket, nb):
     return {f"NB{k}": v for k, v in sorted(out.items())}
 
 
+NEXT_ROWS = ("pattern_cache", "marching_cubes", "edge_postpass")
 DTYPES = {"fp32": "f32", "fp64": "f64", "mixed_fp16": "f16x3+f32", "mixed_bf16": "bf16x3+f32"}
 
 
@@ -289,6 +368,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other precisions and the leave-one-slice-out timing")
+    ap.add_argument("--edge-only", action="store_true",
+                    help="only the edge post-pass on the volume of one untimed execute "
+                         "(for profiling its kernels)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -306,6 +388,26 @@ def main():
     t0 = time.time()
     s, e = W.make_inputs(w)
     print(f"# inputs {w.name}: {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    if args.edge_only:
+        import torch
+        import paper_2303_09523_amd as P
+        st = torch.from_numpy(s).cuda()
+        et = torch.from_numpy(e).cuda() if e is not None else None
+        pk = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
+                    refine_max=args.refine_max, refine_tol=args.refine_tol)
+        vol, _, _ = pk.execute(st, w.vario, et)
+        pk.close()
+        rec = edge_postpass_record(w, vol, args, reps=args.steps)
+        if args.calib_copy > 0:
+            src = torch.empty(args.calib_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            rec["calibration"] = {"copy_bytes": int(src.numel() * 4)}
+        print(json.dumps({"workload": w.name, "edge_postpass": rec}))
+        return
 
     cpu = None
     sample = None
@@ -503,6 +605,7 @@ def main():
         del tris, ids
         print(f"# marching cubes: {mesh_ms:.3f} ms, {ntri} triangles", file=sys.stderr,
               flush=True)
+        others["edge_postpass"] = edge_postpass_record(w, vol, args)
         wl = W.workload("loso_16x128")
         sl_, _ = W.make_inputs(wl)
         slt = torch.from_numpy(sl_).to(dev)
@@ -676,7 +779,10 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "plain_fp32": plain,
-        "batched_variants": others,
+        "batched_variants": {k: v for k, v in others.items() if k not in NEXT_ROWS},
+        # the rows beyond the path: full-window weight cache, marching cubes and
+        # the paper's edge post-pass
+        "next_rows": {k: others[k] for k in NEXT_ROWS if k in others},
         "loso": loso,
         "variogram_fit": fit,
         "precision_study": study,

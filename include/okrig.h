@@ -162,13 +162,15 @@ typedef struct {
   int64_t n_fp64_fallback;    /* systems re-solved in FP64 */
   int64_t n_nonpositive_pivot;/* systems with a non-positive pivot in the first pass */
   double  max_kappa_est;      /* largest pivot-ratio condition estimate */
-  double  phase_ms[11];       /* with profiling on: summed device time per phase since the
+  double  phase_ms[13];       /* with profiling on: summed device time per phase since the
                                  last okr_stats_get: 0 placement, 1 tables, 2 selection,
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
                                  6 plain per-voxel kernel, 7 leave-one-slice-out,
                                  8 full-window pattern weights + application,
-                                 9 marching cubes, 10 edge post-pass */
-  int64_t phase_calls[11];    /* launches timed per phase */
+                                 9 marching cubes, edge post-pass: 10 shearlet
+                                 coefficients, 11 edge thinning, 12 chain tracing and
+                                 re-routing (with the copy of the input to the output) */
+  int64_t phase_calls[13];    /* launches timed per phase */
   int64_t n_not_converged;    /* systems whose FP64 re-solve also met a non-positive pivot */
   int64_t n_refine_unconverged; /* systems whose correction left refine_tol unmet (each
                                    re-solved in FP64, so also in n_fp64_fallback) */
@@ -187,8 +189,10 @@ typedef struct {
 #define OKR_PHASE_LOSO 7
 #define OKR_PHASE_PATTERN 8
 #define OKR_PHASE_MESH 9
-#define OKR_PHASE_EDGE 10
-#define OKR_NUM_PHASES 11
+#define OKR_PHASE_EDGE_SHEAR 10
+#define OKR_PHASE_EDGE_THIN 11
+#define OKR_PHASE_EDGE_TRACE 12
+#define OKR_NUM_PHASES 13
 
 /* Create a plan for one problem shape. `hip_stream` is a hipStream_t (NULL =
  * the default stream). Validates every field (OKR_E_INVALID_ARG / SHAPE /

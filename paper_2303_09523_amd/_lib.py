@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "OKR_OK", 1: "OKR_E_INVALID_ARG", 2: "OKR_E_SHAPE", 3: "OKR_E
                 7: "OKR_E_NOT_CONVERGED", 8: "OKR_E_CAPACITY"}
 MODELS = {"spherical": 0, "exponential": 1, "gaussian": 2}
 PHASES = ["place", "tables", "select", "bucket", "solve", "fallback", "plain", "loso", "pattern",
-          "mesh", "edge"]
+          "mesh", "edge_shear", "edge_thin", "edge_trace"]
 PRECISIONS = {"fp32": 0, "mixed_fp16": 1, "mixed_bf16": 2, "fp64": 3}
 ALGOS = {"batched": 0, "plain": 1, "pattern": 2}
 
@@ -45,8 +45,8 @@ class Stats(C.Structure):
     _fields_ = [("n_systems", C.c_int64), ("n_kriged", C.c_int64), ("bucket", C.c_int64 * 128),
                 ("n_floor_filled", C.c_int64), ("n_refined", C.c_int64),
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
-                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 11),
-                ("phase_calls", C.c_int64 * 11), ("n_not_converged", C.c_int64),
+                ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 13),
+                ("phase_calls", C.c_int64 * 13), ("n_not_converged", C.c_int64),
                 ("n_refine_unconverged", C.c_int64), ("kappa_window", C.c_double)]
 
 

@@ -82,5 +82,15 @@ constexpr TapTable kTapTable = make_taps();
 constexpr int kCwD1[8] = {1, 1, 0, -1, -1, -1, 0, 1};
 constexpr int kCwD2[8] = {0, 1, 1, 1, 0, -1, -1, -1};
 
+// The same offsets packed two bits per direction (offset + 1), so device code
+// can look them up in a register instead of a table in memory.
+constexpr unsigned pack_offsets(const int (&d)[8]) {
+  unsigned v = 0;
+  for (int i = 0; i < 8; ++i) v |= (unsigned)(d[i] + 1) << (2 * i);
+  return v;
+}
+constexpr unsigned kCwPack1 = pack_offsets(kCwD1);
+constexpr unsigned kCwPack2 = pack_offsets(kCwD2);
+
 }  // namespace edge
 }  // namespace okr

@@ -45,6 +45,10 @@ __device__ __forceinline__ int normal2(const EdgeArgs& a, int k) {
   return (int)((a.n2 >> (4 * k)) & 15u) - 1;
 }
 
+// clockwise neighbour offsets (d1, d2) of direction d in 0..7
+__device__ __forceinline__ int cw_d1(int d) { return (int)((edge::kCwPack1 >> (2 * d)) & 3u) - 1; }
+__device__ __forceinline__ int cw_d2(int d) { return (int)((edge::kCwPack2 >> (2 * d)) & 3u) - 1; }
+
 // acc[k] += tap(k, I2, I1) * x for every orientation whose tap is nonzero.
 // Zero taps are skipped: for finite inputs adding a signed zero to a sum that
 // starts at +0 never changes it.
@@ -68,12 +72,15 @@ __device__ __forceinline__ void tap_j(double (&acc)[kShearRows][kOrient], double
 // Input rows in order, and within a row the columns in order: for each output
 // row this visits its taps with d2 outer and d1 inner.
 template <int RHO, int I1>
-__device__ __forceinline__ void tap_rc(double (&acc)[kShearRows][kOrient], const float* col,
-                                       const long long* rowoff, const long long* coloff) {
-  const double x = (double)col[rowoff[RHO] + coloff[I1]];
+__device__ __forceinline__ void tap_rc(double (&acc)[kShearRows][kOrient], const float* vol,
+                                       unsigned xs, const long long* rowoff,
+                                       const long long* coloff) {
+  // wave-uniform row pointer plus the lane's 32-bit byte offset
+  const char* row = reinterpret_cast<const char*>(vol + (rowoff[RHO] + coloff[I1]));
+  const double x = (double)*reinterpret_cast<const float*>(row + xs);
   tap_j<RHO, I1, 0>(acc, x);
   if constexpr (I1 + 1 < kTaps) {
-    tap_rc<RHO, I1 + 1>(acc, col, rowoff, coloff);
+    tap_rc<RHO, I1 + 1>(acc, vol, xs, rowoff, coloff);
   } else if constexpr (RHO + 1 < kShearRows + 2 * kR) {
     // Finish each row before the next: the sums are pinned here (otherwise
     // the compiler sinks all arithmetic below the bounds checks of the stores
@@ -83,7 +90,7 @@ __device__ __forceinline__ void tap_rc(double (&acc)[kShearRows][kOrient], const
     for (int j = 0; j < kShearRows; ++j)
 #pragma unroll
       for (int k = 0; k < kOrient; ++k) asm volatile("" : "+v"(acc[j][k]));
-    tap_rc<RHO + 1, 0>(acc, col, rowoff, coloff);
+    tap_rc<RHO + 1, 0>(acc, vol, xs, rowoff, coloff);
   }
 }
 
@@ -91,10 +98,11 @@ __global__ __launch_bounds__(64 * kShearWaves) void edge_shear_kernel(EdgeArgs a
   const int lane = threadIdx.x & 63;
   const int x = blockIdx.x * 64 + lane;
   const int y = __builtin_amdgcn_readfirstlane(blockIdx.y * kShearWaves + (threadIdx.x >> 6));
-  const int z0 = blockIdx.z * kShearRows;
+  const int z0 = __builtin_amdgcn_readfirstlane(blockIdx.z * kShearRows);
   if (y >= a.ny) return;
   const long long nx = a.nx, plane = (long long)a.ny * a.nx;
-  const int xs = x < a.nx ? x : a.nx - 1;   // lanes past the edge load a valid pixel
+  // byte offset of the lane's image; lanes past the edge load a valid pixel
+  const unsigned xs = 4u * (unsigned)(x < a.nx ? x : a.nx - 1);
   // border replicated: clamped row and column offsets
   long long rowoff[kShearRows + 2 * kR], coloff[kTaps];
 #pragma unroll
@@ -114,7 +122,7 @@ __global__ __launch_bounds__(64 * kShearWaves) void edge_shear_kernel(EdgeArgs a
   for (int j = 0; j < kShearRows; ++j)
 #pragma unroll
     for (int k = 0; k < kOrient; ++k) acc[j][k] = 0.0;
-  tap_rc<0, 0>(acc, a.volume + xs, rowoff, coloff);
+  tap_rc<0, 0>(acc, a.volume, xs, rowoff, coloff);
   if (x >= a.nx) return;
 #pragma unroll
   for (int j = 0; j < kShearRows; ++j) {
@@ -189,8 +197,18 @@ struct Bitmap {
   }
 };
 
-struct WindowLds {
-  int z[kWindow], y[kWindow], t[kWindow];
+// Full windows wait in a queue in LDS (pixel index z * ny + y of each of
+// their 16 pixels) and are checked kQueue at a time, one lane per window,
+// with all orientation loads in flight together. Windows only read the
+// orientations of the shearlet pass and change the output volume and maps,
+// never the bitmap the chains follow, so checking them after the chains that
+// produced them, in queue order, gives the same result as checking each as
+// soon as it is complete.
+constexpr int kQueue = 64;
+
+struct WindowQueue {
+  uint32_t pix[kQueue][kWindow];
+  uint8_t th[kQueue][kWindow];
 };
 
 __device__ __forceinline__ float median3(float a, float b, float c) {
@@ -204,59 +222,61 @@ __device__ __forceinline__ float median3(float a, float b, float c) {
   return b;
 }
 
-// Steps 4 and 5 on a noisy window (one lane): orientations in w.t are the
-// ones the shearlet pass found.
-__device__ void reroute_window(const EdgeArgs& a, int x, const WindowLds& w) {
-  const long long nx = a.nx, ny = a.ny;
+// Steps 4 and 5 on noisy window q of the queue (one lane).
+__device__ void reroute_window(const EdgeArgs& a, int x, const WindowQueue& wq, int q) {
+  const long long nx = a.nx;
   const int H = a.nz, Wd = a.ny;
+  const uint32_t* pix = wq.pix[q];
+  const uint8_t* th = wq.th[q];
   // representative orientation: the most frequent, ties to the one seen first
   int best = -1, rep = 0;
   for (int i = 0; i < kWindow; ++i) {
     int c = 0;
-    for (int j = 0; j < kWindow; ++j) c += w.t[j] == w.t[i];
+    for (int j = 0; j < kWindow; ++j) c += th[j] == th[i];
     if (c > best) {
       best = c;
-      rep = w.t[i];
+      rep = th[i];
     }
   }
   // edge tangent: the rounded normal turned by 90 degrees, pointing from the
   // window's first pixel toward its last
   int t1 = -normal2(a, rep), t2 = normal1(a, rep);
-  const int dr = w.z[kWindow - 1] - w.z[0], dc = w.y[kWindow - 1] - w.y[0];
-  if (t1 * dc + t2 * dr < 0) {
+  const int z0 = (int)(pix[0] / (uint32_t)Wd), y0 = (int)(pix[0] % (uint32_t)Wd);
+  const int zl = (int)(pix[kWindow - 1] / (uint32_t)Wd), yl = (int)(pix[kWindow - 1] % (uint32_t)Wd);
+  if (t1 * (yl - y0) + t2 * (zl - z0) < 0) {
     t1 = -t1;
     t2 = -t2;
   }
-  // the 3 neighbours on each side of the tangent, in clockwise order
-  int s1[2][3], s2[2][3], ns[2] = {0, 0};
+  // the 3 neighbours on each side of the tangent (cross product t x d > 0,
+  // then < 0), in clockwise order; the two sides are disjoint, so both
+  // medians read values the other does not write
+  int o1[6], o2[6], ns0 = 0, ns1 = 3;
+#pragma unroll
   for (int d = 0; d < 8; ++d) {
-    const int d1 = edge::kCwD1[d], d2 = edge::kCwD2[d];
+    const int d1 = cw_d1(d), d2 = cw_d2(d);
     const int cr = t1 * d2 - t2 * d1;
-    const int side = cr > 0 ? 0 : (cr < 0 ? 1 : -1);
-    if (side >= 0) {
-      s1[side][ns[side]] = d1;
-      s2[side][ns[side]] = d2;
-      ++ns[side];
+    if (cr > 0) {
+      o1[ns0] = d1;
+      o2[ns0] = d2;
+      ++ns0;
+    } else if (cr < 0) {
+      o1[ns1] = d1;
+      o2[ns1] = d2;
+      ++ns1;
     }
   }
-  int qz = w.z[0], qy = w.y[0];
+  int qz = z0, qy = y0;
   for (int m = 1; m < kWindow - 1; ++m) {
-    const int pz = w.z[m], py = w.y[m];
-    const long long ip = ((long long)pz * ny + py) * nx + x;
-    if (w.t[m] == rep) {
-      qz = pz;
-      qy = py;
-      if (a.orient_out) a.orient_out[ip] = (uint8_t)rep;
-      continue;
-    }
+    const int pz = (int)(pix[m] / (uint32_t)Wd), py = (int)(pix[m] % (uint32_t)Wd);
+    const long long ip = (long long)pix[m] * nx + x;
     const int nz_ = qz + t2, ny_ = qy + t1;
-    if (nz_ < 0 || nz_ >= H || ny_ < 0 || ny_ >= Wd) {
+    if (th[m] == rep || nz_ < 0 || nz_ >= H || ny_ < 0 || ny_ >= Wd) {
       qz = pz;
       qy = py;
       if (a.orient_out) a.orient_out[ip] = (uint8_t)rep;
       continue;
     }
-    const long long in = ((long long)nz_ * ny + ny_) * nx + x;
+    const long long in = ((long long)nz_ * Wd + ny_) * nx + x;
     if (a.edge_out) {
       a.edge_out[ip] = 0;
       a.edge_out[in] = 1;
@@ -264,51 +284,69 @@ __device__ void reroute_window(const EdgeArgs& a, int x, const WindowLds& w) {
     if (a.orient_out) a.orient_out[in] = (uint8_t)rep;
     qz = nz_;
     qy = ny_;
+    long long idx[6];
+    bool inside[2] = {true, true};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int zz = nz_ + o2[j], yy = ny_ + o1[j];
+      const bool ok = zz >= 0 && zz < H && yy >= 0 && yy < Wd;
+      inside[j / 3] = inside[j / 3] && ok;
+      idx[j] = ok ? ((long long)zz * Wd + yy) * nx + x : in;
+    }
+    float v[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] = a.out[idx[j]];
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
-      bool inside = true;
-      long long idx[3];
-      for (int j = 0; j < 3; ++j) {
-        const int zz = nz_ + s2[side][j], yy = ny_ + s1[side][j];
-        inside = inside && zz >= 0 && zz < H && yy >= 0 && yy < Wd;
-        idx[j] = ((long long)zz * ny + yy) * nx + x;
-      }
-      if (!inside) continue;
-      const float med = median3(a.out[idx[0]], a.out[idx[1]], a.out[idx[2]]);
-      for (int j = 0; j < 3; ++j) a.out[idx[j]] = med;
+      if (!inside[side]) continue;
+      const float med = median3(v[3 * side], v[3 * side + 1], v[3 * side + 2]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) a.out[idx[3 * side + j]] = med;
     }
   }
 }
 
-// A full window of 16 chain pixels; lane l < 16 holds pixel l in (wz, wy).
-__device__ void check_window(const EdgeArgs& a, int x, int lane, int wz, int wy, WindowLds& w) {
-  int th = 0;
-  if (lane < kWindow) th = a.theta[((long long)wz * a.ny + wy) * a.nx + x];
-  const int prev = __shfl_up(th, 1);
-  const unsigned long long chg = __ballot(lane >= 1 && lane < kWindow && th != prev);
-  if (__popcll(chg) < kMinChanges) return;
-  if (lane < kWindow) {
-    w.z[lane] = wz;
-    w.y[lane] = wy;
-    w.t[lane] = th;
+// Check the nq queued windows: lane w loads window w's orientations and
+// counts their changes; noisy windows are then re-routed in queue order.
+__device__ void flush_windows(const EdgeArgs& a, int x, int lane, WindowQueue& wq, int nq) {
+  bool noisy = false;
+  if (lane < nq) {
+    int t[kWindow];
+#pragma unroll
+    for (int i = 0; i < kWindow; ++i) t[i] = a.theta[(long long)wq.pix[lane][i] * a.nx + x];
+    int changes = 0;
+#pragma unroll
+    for (int i = 0; i < kWindow; ++i) {
+      wq.th[lane][i] = (uint8_t)t[i];
+      if (i > 0) changes += t[i] != t[i - 1];
+    }
+    noisy = changes >= kMinChanges;
   }
+  unsigned long long mask = __ballot(noisy);
   __syncthreads();
-  if (lane == 0) reroute_window(a, x, w);
+  while (mask) {
+    const int q = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    if (lane == 0) reroute_window(a, x, wq, q);
+  }
   __syncthreads();
 }
 
 template <bool kLds>
 __global__ __launch_bounds__(64) void edge_trace_kernel(EdgeArgs a) {
   extern __shared__ uint32_t lds_bits[];
-  __shared__ WindowLds win;
+  __shared__ WindowQueue wq;
   const int x = blockIdx.x, lane = threadIdx.x;
   const long long wr = a.wr, nwords = (long long)(a.nz + 2) * wr;
   const long long last_word = (long long)(a.nz + 1) * wr;   // end of padded row nz
   const Bitmap<kLds> bm{lds_bits, a.bits + x, a.nx};
   if (kLds) {
+#pragma unroll 8
     for (long long i = lane; i < nwords; i += 64) lds_bits[i] = a.bits[i * a.nx + x];
     __syncthreads();
   }
-  int wz = 0, wy = 0;   // window pixel held by this lane
+  uint32_t wpix = 0;    // pixel (z * ny + y) of window slot `lane`
+  int nq = 0;           // windows queued
   long long scan = wr;  // first word of padded row 1
   for (;;) {
     // next chain start: the first remaining edge pixel in row-major order
@@ -331,12 +369,8 @@ __global__ __launch_bounds__(64) void edge_trace_kernel(EdgeArgs a) {
     int row = (int)(wi / wr);
     int cb = (int)(wi % wr) * 32 + (__ffs((int)wv) - 1);
     if (lane == 0) bm.clear(wi, cb & 31);
-    int slot = 0;
-    if (lane == slot) {
-      wz = row - 1;
-      wy = cb - 1;
-    }
-    ++slot;
+    if (lane == 0) wpix = (uint32_t)(row - 1) * (uint32_t)a.ny + (uint32_t)(cb - 1);
+    int slot = 1;
     int last = -1;
     for (;;) {
       // first remaining neighbour clockwise, starting three steps
@@ -345,25 +379,31 @@ __global__ __launch_bounds__(64) void edge_trace_kernel(EdgeArgs a) {
       const int dir = (start + lane) & 7;
       bool av = false;
       if (lane < 8) {
-        const int nr = row + edge::kCwD2[dir], nc = cb + edge::kCwD1[dir];
+        const int nr = row + cw_d2(dir), nc = cb + cw_d1(dir);
         av = (bm.word((long long)nr * wr + (nc >> 5)) >> (nc & 31)) & 1u;
       }
       const unsigned long long bal = __ballot(av);
       if (!bal) break;
       const int d = (start + __ffsll((long long)bal) - 1) & 7;
-      row += edge::kCwD2[d];
-      cb += edge::kCwD1[d];
+      row += cw_d2(d);
+      cb += cw_d1(d);
       last = d;
       if (lane == 0) bm.clear((long long)row * wr + (cb >> 5), cb & 31);
-      if (lane == slot) {
-        wz = row - 1;
-        wy = cb - 1;
-      }
+      if (lane == slot) wpix = (uint32_t)(row - 1) * (uint32_t)a.ny + (uint32_t)(cb - 1);
       if (++slot == kWindow) {
-        check_window(a, x, lane, wz, wy, win);
+        if (lane < kWindow) wq.pix[nq][lane] = wpix;
         slot = 0;
+        if (++nq == kQueue) {
+          __syncthreads();
+          flush_windows(a, x, lane, wq, nq);
+          nq = 0;
+        }
       }
     }
+  }
+  if (nq > 0) {
+    __syncthreads();
+    flush_windows(a, x, lane, wq, nq);
   }
 }
 
@@ -385,12 +425,18 @@ hipError_t launch_edge_nms(const EdgeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_edge_trace(const EdgeArgs& a, size_t lds_bytes, hipStream_t s) {
-  if (lds_bytes > 0)
-    hipLaunchKernelGGL(edge_trace_kernel<true>, dim3(a.nx), dim3(64), lds_bytes, s, a);
+bool launch_edge_trace(const EdgeArgs& a, int lds_limit, hipStream_t s, hipError_t* err) {
+  // the bitmap of one image in LDS when it fits in 64 KB (and the device's
+  // limit) beside the window queue, else traced in place in global memory
+  const size_t bitmap = sizeof(uint32_t) * (size_t)(a.nz + 2) * (size_t)a.wr;
+  const size_t cap = lds_limit < 65536 ? (size_t)lds_limit : 65536;
+  const bool in_lds = bitmap + sizeof(WindowQueue) + 256 <= cap;
+  if (in_lds)
+    hipLaunchKernelGGL(edge_trace_kernel<true>, dim3(a.nx), dim3(64), bitmap, s, a);
   else
     hipLaunchKernelGGL(edge_trace_kernel<false>, dim3(a.nx), dim3(64), 0, s, a);
-  return hipGetLastError();
+  *err = hipGetLastError();
+  return in_lds;
 }
 
 }  // namespace okr

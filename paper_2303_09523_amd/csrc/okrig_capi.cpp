@@ -974,7 +974,8 @@ okr_status okr_edge_postpass(okr_plan* p, const float* d_volume, float* d_out, d
   const int wr = okr::edge_words_per_row((int)ny);
   const long long words = (nz + 2) * wr;
   if (nz < 1 || vox <= 0) return OKR_OK;
-  if (nz + 2 > 0x7fffffffLL || words > 0x7fffffffLL || (words + 3) / 4 > 0x7fffffffLL)
+  if (nz + 2 > 0x7fffffffLL || words > 0x7fffffffLL || (words + 3) / 4 > 0x7fffffffLL ||
+      nz * ny > 0xffffffffLL)
     return fail(p, OKR_E_SHAPE, "volume too large for the edge post-pass");
   const char* vb = reinterpret_cast<const char*>(d_volume);
   const char* ob = reinterpret_cast<const char*>(d_out);
@@ -1019,18 +1020,22 @@ okr_status okr_edge_postpass(okr_plan* p, const float* d_volume, float* d_out, d
     a.n1 |= (uint32_t)(n1[k] + 1) << (4 * k);
     a.n2 |= (uint32_t)(n2[k] + 1) << (4 * k);
   }
-  // the bitmap of one image in LDS when it fits in 64 KB with the window
-  // record (and below the device's limit), else traced in place in global
-  // memory
-  const size_t lds = sizeof(uint32_t) * (size_t)words;
-  const size_t lds_cap = std::min<size_t>((size_t)p->edge_lds_max, 65536);
-  const size_t lds_use = lds + 512 <= lds_cap ? lds : 0;
-  PhaseTimer t(p, OKR_PHASE_EDGE);
-  if (d_out != d_volume)
-    OKR_HIP(p, hipMemcpyAsync(d_out, d_volume, bytes, hipMemcpyDeviceToDevice, p->stream));
-  OKR_HIP(p, okr::launch_edge_shear(a, p->stream));
-  OKR_HIP(p, okr::launch_edge_nms(a, p->stream));
-  OKR_HIP(p, okr::launch_edge_trace(a, lds_use, p->stream));
+  {
+    PhaseTimer t(p, OKR_PHASE_EDGE_SHEAR);
+    OKR_HIP(p, okr::launch_edge_shear(a, p->stream));
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_EDGE_THIN);
+    OKR_HIP(p, okr::launch_edge_nms(a, p->stream));
+  }
+  {
+    PhaseTimer t(p, OKR_PHASE_EDGE_TRACE);
+    if (d_out != d_volume)
+      OKR_HIP(p, hipMemcpyAsync(d_out, d_volume, bytes, hipMemcpyDeviceToDevice, p->stream));
+    hipError_t err = hipSuccess;
+    okr::launch_edge_trace(a, p->edge_lds_max, p->stream, &err);
+    OKR_HIP(p, err);
+  }
   return OKR_OK;
 }
 
