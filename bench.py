@@ -278,7 +278,7 @@ TRAFFIC_SOURCES = ["okrig_internal.h", "solver_core.h", "solver_refine.h", "kern
 
 
 MESH_TRAFFIC_SOURCES = ["okrig_internal.h", "kernels_mcubes.hip"]
-EDGE_TRAFFIC_SOURCES = ["okrig_internal.h", "edge_filters.h", "kernels_edge.hip"]
+EDGE_TRAFFIC_SOURCES = ["edge_internal.h", "edge_filters.h", "kernels_edge.hip"]
 
 
 def _source_hash(names) -> str:

@@ -21,7 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "edge_filters.h"
-#include "okrig_internal.h"
+#include "edge_internal.h"
 
 namespace okr {
 namespace {

@@ -16,6 +16,7 @@
 
 #include "../../include/okrig.h"
 #include "edge_filters.h"
+#include "edge_internal.h"
 #include "okrig_internal.h"
 
 namespace okr {

@@ -143,26 +143,6 @@ hipError_t launch_plain(const float* slices, const uint8_t* edge, float* volume,
                         const Geometry& g, const SelectRule& rule, const Vario& v, TableSet tab,
                         int refine, int num_cu, hipStream_t s);
 
-// ---- edge post-pass (kernels_edge.hip) ----
-struct EdgeArgs {
-  const float* volume;  // input volume [nz][ny][nx]
-  float* out;           // adjusted volume: a copy of the input, or the input itself
-  double* mag;          // M = max_k |SH_k| [nz][ny][nx]
-  uint8_t* theta;       // first argmax orientation [nz][ny][nx]
-  uint32_t* bits;       // per-image edge bitmaps [(nz + 2) * wr][nx]
-  uint8_t* edge_out;    // edge map [nz][ny][nx] (nullable)
-  uint8_t* orient_out;  // orientation map [nz][ny][nx] (nullable)
-  double tau;           // edge threshold on M
-  int nz, ny, nx;
-  int wr;               // bitmap words per padded row
-  uint32_t n1, n2;      // rounded normal of orientation k: 4-bit field k holds n + 1
-};
-int edge_words_per_row(int ny);
-hipError_t launch_edge_shear(const EdgeArgs& a, hipStream_t s);
-hipError_t launch_edge_nms(const EdgeArgs& a, hipStream_t s);
-// lds_bytes > 0: each image's bitmap is held in that much LDS; 0: in place
-hipError_t launch_edge_trace(const EdgeArgs& a, size_t lds_bytes, hipStream_t s);
-
 // ---- marching cubes (mcubes_table.cpp, kernels_mcubes.hip) ----
 constexpr int kMcMaxTri = 5;     // triangles of one cube configuration, at most
 constexpr int kMcRows = 64;      // rows of one wave's strip of 64 cubes (at most 64)

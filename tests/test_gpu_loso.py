@@ -233,3 +233,34 @@ def test_loso_full_size_drift_with_masks_vs_oracle():
     print(f"full drift: loss {L:.10e} vs {L_o:.10e}; grad {g} vs {g_o}", flush=True)
     assert abs(L - L_o) <= 1e-9 * abs(L_o)
     np.testing.assert_allclose(g, g_o, rtol=1e-4)
+
+
+@pytest.mark.slow
+def test_full_fit_trajectory_vs_golden():
+    """The 200-step Adam fit of the variogram on the 16 x 128^2 field workload
+    (exponential model from (0.1, 1.0, 2.0), lr 0.05) against the FP64
+    oracle's trajectory stored by tests/golden/make_loso_fit.py: final loss
+    within 1e-4 relative, nugget/sill and range within 1e-2 relative."""
+    import json
+    import os
+    import torch
+    import workloads as W
+    from paper_2303_09523_amd.autograd import fit_variogram
+    import paper_2303_09523_amd as P
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "loso_fit_16x128.json")))
+    w = W.workload(gold["workload"])
+    s, _ = W.make_inputs(w)
+    plan = P.Plan(w.m, w.m, w.nslices, 2, w.radius, 4)
+    traj = fit_variogram(plan, torch.from_numpy(s).cuda(), tuple(gold["theta0"]),
+                         steps=gold["steps"], lr=gold["lr"], model=gold["model"])
+    plan.close()
+    assert len(traj) == len(gold["loss"]) == gold["steps"] + 1
+    Lg, tg = traj[-1]
+    Lr, tr = gold["loss"][-1], np.array(gold["theta"][-1])
+    print("gpu", Lg, tg, "oracle", Lr, tr, flush=True)
+    assert abs(Lg - Lr) <= 1e-4 * abs(Lr)
+    assert abs(tg[0] / tg[1] - tr[0] / tr[1]) <= 1e-2 * abs(tr[0] / tr[1])
+    assert abs(tg[2] - tr[2]) <= 1e-2 * abs(tr[2])
+    # the loss falls along the whole trajectory as the oracle's does
+    assert abs(traj[0][0] - gold["loss"][0]) <= 1e-6 * abs(gold["loss"][0])
