@@ -27,9 +27,10 @@ Prints ONE JSON line. Extra keys:
                     each with its accuracy on the same sample
   next_rows         pattern_cache (full-window weight cache), marching_cubes and
                     edge_postpass, below
-  plain_fp32        the per-voxel comparison kernel
+  plain_fp32        the per-voxel comparison kernel (FP32 with its FP64-residual
+                    refinement step, at the same per-voxel 1e-5 bar), on a slab
   other_configs     the small and the edge-preserved workloads: batched FP32,
-                    refined mixed and the plain per-voxel kernel
+                    refined mixed and the refined plain per-voxel kernel
   precision_study   the ill-conditioned Gaussian workload in every precision
                     mode, with routing counts and per-voxel errors
   loso              leave-one-slice-out loss + adjoint gradient timing on the
@@ -664,7 +665,8 @@ def main():
                    "n_fp64_resolved": sv["n_fp64_fallback"], "n_refined": sv["n_refined"],
                    "n_refine_unconverged": sv["n_refine_unconverged"],
                    "n_nonpositive_pivot": sv["n_nonpositive_pivot"],
-                   "kappa_window": sv["kappa_window"], "max_kappa_est": sv["max_kappa_est"]}
+                   "kappa_window": sv["kappa_window"], "max_kappa_est": sv["max_kappa_est"],
+                   "direct_fp64": sv["direct_fp64"]}
             acc3 = _sample_accuracy(w3, s3, samp3, v3, None)
             if acc3:
                 ent.update(acc3)
@@ -687,7 +689,7 @@ def main():
             for label, prec, algo, rmax, tol in (("batched_fp32", "fp32", "batched", 0, 0.0),
                                                  ("batched_mixed_refined", "mixed_fp16",
                                                   "batched", 1, 1e-5),
-                                                 ("plain_fp32", "fp32", "plain", 0, 0.0)):
+                                                 ("plain_fp32_refined", "fp32", "plain", 1, 0.0)):
                 px = P.Plan(wx.m, wx.m, wx.nslices, wx.upsample, wx.radius, 4, prec, algo,
                             refine_max=rmax, refine_tol=tol)
                 if algo != "plain":

@@ -116,8 +116,6 @@ typedef struct {
                            conditioned (eigenvalue interlacing). With u the unit
                            roundoff of the factorisation (2^-24 FP32, 2^-22 split
                            FP16, 2^-16 split BF16):
-                           FP32: kappa_w * 2^-24 > refine_tol sends every system
-                           to the FP64 re-solve;
                            MIXED_* with refine_max = 0: a system whose indicator
                            kappa_w*u*s / max(|z_hat|, 0.01*max|known voxel|)
                            exceeds refine_tol for some target (s: the power of
@@ -132,6 +130,15 @@ typedef struct {
                            exceeds refine_tol * max(|z_hat|, 0.01*max|known voxel|)
                            for some target is unconverged: re-solved in FP64,
                            flagged (bit 32) and counted (n_refine_unconverged).
+                           Where the full-window system itself fails its test
+                           (FP32: kappa_w*2^-24 > refine_tol; refine_max = 0:
+                           kappa_w*u > refine_tol; refine_max = 1:
+                           min(1, 10*kappa_w*u)*kappa_w*u > refine_tol), every
+                           system is solved in FP64 directly instead, flagged
+                           (bit 4) and counted in n_fp64_fallback as re-solved
+                           (results equal the FP64 launch bit for bit; the
+                           environment variable OKR_NO_DIRECT_FP64=1 keeps the
+                           low-precision pass with its per-system checks).
                            Ignored by FP64. Systems with a non-positive pivot are
                            always re-solved in FP64. */
   int32_t refine_max;   /* MIXED_*: 0 = no correction (the low-precision
@@ -177,6 +184,8 @@ typedef struct {
   double  kappa_window;       /* condition number of the full-window covariance matrix
                                  used by the last execute's precision control (0 if
                                  refine_tol was 0) */
+  int32_t direct_fp64;        /* 1 if the last execute solved every system in FP64
+                                 directly (see refine_tol) */
 } okr_stats;
 
 #define OKR_PHASE_PLACE 0

@@ -256,6 +256,7 @@ class Plan:
                 "n_nonpositive_pivot": s.n_nonpositive_pivot, "max_kappa_est": s.max_kappa_est,
                 "n_not_converged": s.n_not_converged,
                 "n_refine_unconverged": s.n_refine_unconverged, "kappa_window": s.kappa_window,
+                "direct_fp64": bool(s.direct_fp64),
                 "phase_ms": dict(zip(_lib.PHASES, list(s.phase_ms))),
                 "phase_calls": dict(zip(_lib.PHASES, list(s.phase_calls)))}
 

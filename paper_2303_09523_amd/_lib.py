@@ -47,7 +47,8 @@ class Stats(C.Structure):
                 ("n_fp64_fallback", C.c_int64), ("n_nonpositive_pivot", C.c_int64),
                 ("max_kappa_est", C.c_double), ("phase_ms", C.c_double * 13),
                 ("phase_calls", C.c_int64 * 13), ("n_not_converged", C.c_int64),
-                ("n_refine_unconverged", C.c_int64), ("kappa_window", C.c_double)]
+                ("n_refine_unconverged", C.c_int64), ("kappa_window", C.c_double),
+                ("direct_fp64", C.c_int32)]
 
 
 class OkrError(RuntimeError):

@@ -61,6 +61,7 @@ struct okr_plan {
   // 2-norm condition number of the full-window covariance matrix for the last
   // variogram it was computed for (every system's covariance matrix is a
   // principal submatrix of it, so bounds their condition numbers)
+  bool last_direct64 = false;   // the last execute solved every system in FP64 directly
   bool kw_valid = false;
   okr_variogram kw_vario{};
   double kappa_w = 0.0;
@@ -81,7 +82,7 @@ struct okr_plan {
     float* volume;
     float* variance;
     uint8_t* flags;
-    bool forced;
+    bool forced, no_direct;
     int grid_per_cu, upd;
   } gkey{};
   bool gkey_valid = false;
@@ -329,6 +330,7 @@ okr::SolveArgs solve_args(okr_plan* p, const okr_variogram* v) {
   a.refine_tol = 0.0;
   a.rho_hat = 1.0;
   a.kappa_w = 0.0;
+  a.as_resolve = 0;
   a.upd = 1;
   a.nmax = okr::kHist - 1;
   a.fallback = nullptr;
@@ -462,6 +464,14 @@ namespace {
 bool force_fallback() {
   const char* force = std::getenv("OKR_FORCE_FALLBACK");
   return force && force[0] == '1';
+}
+
+// OKR_NO_DIRECT_FP64=1 keeps the low-precision pass where the precision
+// control would otherwise solve every system in FP64 directly (tests use it
+// to exercise the per-system checks on ill-conditioned windows).
+bool no_direct_fp64() {
+  const char* v = std::getenv("OKR_NO_DIRECT_FP64");
+  return v && v[0] == '1';
 }
 
 // Covariance of lag h (GSLIB convention, the library's variogram models).
@@ -640,26 +650,42 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   //     times |w_t| |h_w| + |phi_t| |Q'nu_w| (h the FP64 residual); a system
   //     where that exceeds refine_tol (same relative measure) is unconverged
   //     and re-solved in FP64.
+  // Where the full-window system itself misses refine_tol by these bounds
+  // (FP32: kappa_w 2^-24; read-out: kappa_w u; corrected: rho_hat kappa_w u,
+  // the first-order error of its weights times rho_hat), the full-window
+  // systems, most systems of a volume, would all be re-solved: every system
+  // is then solved in FP64 directly (and flagged and counted as re-solved).
   // Systems with a non-positive pivot are always re-solved in FP64.
-  const double kw = (p->prob.refine_tol > 0.0 && p->prob.precision != OKR_FP64)
-                        ? window_kappa(p, *vario) : 0.0;
+  const double tol = p->prob.refine_tol;
+  const double kw = (tol > 0.0 && p->prob.precision != OKR_FP64) ? window_kappa(p, *vario) : 0.0;
   a.kappa_w = kw;
   if (p->prob.precision != OKR_FP64) a.fallback = p->fallback;
+  bool direct64 = false;
   if (mixed) {
     a.refine = p->prob.refine_max > 0 ? 1 : 0;
     a.refine_kappa = 0.0;
     a.upd = p->upd >= 0 ? p->upd : (p->prob.precision == OKR_MIXED_BF16 ? 2 : 1);
     const double uf = factor_roundoff(a.upd);
     if (!a.refine) {
-      a.route_tol = p->prob.refine_tol;
+      a.route_tol = tol;
       a.route_scale = kw * uf;
+      direct64 = tol > 0.0 && !(kw * uf <= tol);
     } else {
-      a.refine_tol = p->prob.refine_tol;
+      a.refine_tol = tol;
       a.rho_hat = std::min(1.0, 10.0 * kw * uf);
+      direct64 = tol > 0.0 && !(a.rho_hat * kw * uf <= tol);
     }
-  } else if (p->prob.precision == OKR_FP32 && p->prob.refine_tol > 0.0 &&
-             !(kw * kUnitRoundoff32 <= p->prob.refine_tol)) {
-    a.kappa_limit = 0.0;
+  } else if (p->prob.precision == OKR_FP32) {
+    direct64 = tol > 0.0 && !(kw * kUnitRoundoff32 <= tol);
+  }
+  p->last_direct64 = direct64 && !no_direct_fp64() && !force_fallback();
+  if (p->last_direct64) {
+    a.precision = OKR_FP64;
+    a.fallback = nullptr;
+    a.as_resolve = 1;
+    a.refine = 0;
+  } else if (direct64 && p->prob.precision == OKR_FP32) {
+    a.kappa_limit = 0.0;   // every system re-solved after the FP32 pass
   }
   if (force_fallback() && p->prob.precision != OKR_FP64) {
     a.kappa_limit = 0.0;
@@ -667,7 +693,7 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   }
   {
     PhaseTimer t(p, OKR_PHASE_SOLVE);
-    if (mixed)
+    if (mixed && !p->last_direct64)
       OKR_HIP(p, okr::launch_solve_mixed(a, persistent_grid(p), strm));
     else
       OKR_HIP(p, okr::launch_solve(a, persistent_grid(p), strm));
@@ -683,7 +709,8 @@ bool same_key(const okr_plan::GraphKey& k, const okr_plan::GraphKey& q) {
   return k.v.model == q.v.model && k.v.nugget == q.v.nugget && k.v.sill == q.v.sill &&
          k.v.range == q.v.range && k.slices == q.slices && k.edge == q.edge &&
          k.volume == q.volume && k.variance == q.variance && k.flags == q.flags &&
-         k.forced == q.forced && k.grid_per_cu == q.grid_per_cu && k.upd == q.upd;
+         k.forced == q.forced && k.no_direct == q.no_direct && k.grid_per_cu == q.grid_per_cu &&
+         k.upd == q.upd;
 }
 
 // Capture the launch sequence into a graph (on the plan's private stream) if
@@ -700,6 +727,7 @@ okr_status execute_graph(okr_plan* p, const okr_variogram* vario, const float* d
   key.variance = d_variance;
   key.flags = d_flags;
   key.forced = force_fallback();
+  key.no_direct = no_direct_fp64();
   key.grid_per_cu = p->grid_per_cu;
   key.upd = p->upd;
   if (!p->gkey_valid || !same_key(p->gkey, key)) {
@@ -1161,6 +1189,7 @@ okr_status okr_stats_get(okr_plan* p, okr_stats* out) {
   out->n_not_converged = (int64_t)c.failed;
   out->n_refine_unconverged = (int64_t)c.unconverged;
   out->kappa_window = p->kw_valid ? p->kappa_w : 0.0;
+  out->direct_fp64 = p->last_direct64 ? 1 : 0;
   if (c.nonfinite) return fail(p, OKR_E_NONFINITE, "a known voxel is not finite");
   if (c.bad_input) return fail(p, OKR_E_SHAPE, "a point system has a count outside 1..98");
   if (p->prob.strict && c.failed)

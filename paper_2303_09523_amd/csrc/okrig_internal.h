@@ -111,6 +111,8 @@ struct SolveArgs {
   double* resid;        // leave-one-slice-out: z_hat - z per system
   double* gpart;        // leave-one-slice-out: per-system gradient [3]
   double inv_count;     // 1 / number of held-out voxels
+  int as_resolve;       // 1: this FP64 launch stands in for the re-solve of every system
+                        // (flags and counters as for re-solved systems)
 };
 hipError_t launch_solve(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t launch_solve_fallback(const SolveArgs& a, int grid, hipStream_t s);

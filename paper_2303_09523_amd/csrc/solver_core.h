@@ -881,17 +881,19 @@ __device__ __forceinline__ void finish_system(const SolveArgs& a, int mode, unsi
       if (a.variance) a.variance[o] = (float)var;
     }
   }
+  // re-solved in FP64: the re-solve pass, or an FP64 launch standing in for it
+  const bool resolved = mode == 1 || a.as_resolve;
   if (lane == 0 && a.flags) {
     uint8_t fl = ((cnt & kFloorBit) ? kFlagFloor : 0) | extra_flags;
-    if (mode == 1) fl |= kFlagFp64;
-    if (mode == 1 && bad) fl |= kFlagFailed;
-    if (bad && mode == 0) fl |= kFlagBadPivot;
+    if (resolved) fl |= kFlagFp64;
+    if (resolved && bad) fl |= kFlagFailed;
+    if (bad && !resolved) fl |= kFlagBadPivot;
     if (mode == 0) a.flags[sys] = fl;
     else a.flags[sys] |= fl;
   }
-  if (bad && mode == 0) tally.bad += 1;
-  if (mode == 1) tally.fp64 += 1;
-  if (mode == 1 && bad) tally.failed += 1;
+  if (bad && !resolved) tally.bad += 1;
+  if (resolved) tally.fp64 += 1;
+  if (resolved && bad) tally.failed += 1;
   const float kf = (float)kappa;
   if (kf > tally.kmax && isfinite(kf)) tally.kmax = kf;
 }

@@ -63,23 +63,29 @@ def test_fp32_routes_every_system_when_the_window_bound_misses_the_tolerance():
     v64, w64, _, _ = run_gpu(s, e, 3, 3, vario, precision="fp64")
     # tolerance below kappa_w 2^-24: every system goes to FP64, bit for bit
     vr, wr, fr, sr = run_gpu(s, e, 3, 3, vario, flags=True, refine_tol=0.5 * kw * 2.0 ** -24)
-    assert sr["n_fp64_fallback"] == sr["n_systems"]
+    assert sr["n_fp64_fallback"] == sr["n_systems"] and sr["direct_fp64"]
     assert ((fr & 4) != 0).all()
     np.testing.assert_array_equal(vr, v64)
     np.testing.assert_array_equal(wr, w64)
     # above it: nothing routed, bit for bit the FP32 launch
     vn, wn, fn, sn = run_gpu(s, e, 3, 3, vario, flags=True, refine_tol=2.0 * kw * 2.0 ** -24)
-    assert sn["n_fp64_fallback"] == sn["n_nonpositive_pivot"] == 0
+    assert sn["n_fp64_fallback"] == sn["n_nonpositive_pivot"] == 0 and not sn["direct_fp64"]
     np.testing.assert_array_equal(vn, v32)
     np.testing.assert_array_equal(wn, w32)
 
 
+@pytest.mark.parametrize("direct", [True, False], ids=["direct", "checked"])
 @pytest.mark.parametrize("precision", ["mixed_fp16", "mixed_bf16"])
-def test_corrected_convergence_routing(precision, c3_small):
+def test_corrected_convergence_routing(precision, direct, c3_small, monkeypatch):
     """refine_max = 1 corrects every system; with refine_tol the systems the
     correction cannot bring under it (by the bound) are flagged (32), counted,
     and equal the FP64 launch bit for bit; the others equal the unchecked
-    corrected launch bit for bit; every voxel then meets the mixed bar."""
+    corrected launch bit for bit; every voxel then meets the mixed bar. The
+    full window misses 1e-4 by its bound here, so by default every system is
+    solved in FP64 directly (flagged and counted as re-solved, bit for bit the
+    FP64 launch); OKR_NO_DIRECT_FP64=1 keeps the per-system checks."""
+    if not direct:
+        monkeypatch.setenv("OKR_NO_DIRECT_FP64", "1")
     s, e, vol_o, var_o = c3_small
     f, r = 4, 3
     tol = 1e-4
@@ -96,6 +102,11 @@ def test_corrected_convergence_routing(precision, c3_small):
     assert (routed >= unconv).all()
     assert sr["n_fp64_fallback"] == routed.sum()
     assert s0["n_refined"] + s0["n_nonpositive_pivot"] == s0["n_systems"]
+    assert sr["direct_fp64"] == direct
+    if direct:
+        assert routed.all() and sr["n_refined"] == 0 and not unconv.any()
+    else:
+        assert unconv.sum() > 0
     for g in range(s.shape[0] - 1):
         for t in range(1, f):
             z = g * f + t
@@ -111,12 +122,16 @@ def test_corrected_convergence_routing(precision, c3_small):
     assert ev.max() <= 1e-4
 
 
+@pytest.mark.parametrize("direct", [True, False], ids=["direct", "checked"])
 @pytest.mark.parametrize("precision", ["mixed_fp16", "mixed_bf16"])
-def test_readout_routing_meets_the_tolerance(precision, c3_small):
+def test_readout_routing_meets_the_tolerance(precision, direct, c3_small, monkeypatch):
     """refine_max = 0 with refine_tol: systems whose error indicator exceeds
     it are re-solved in FP64 (bit for bit the FP64 launch), the others keep
     the read-out (bit for bit the unrouted launch), and every voxel meets the
-    tolerance."""
+    tolerance (by default solved in FP64 directly, as the full window misses
+    it; OKR_NO_DIRECT_FP64=1 keeps the per-system routing)."""
+    if not direct:
+        monkeypatch.setenv("OKR_NO_DIRECT_FP64", "1")
     s, e, vol_o, var_o = c3_small
     f, r = 4, 3
     tol = 1e-4
@@ -127,6 +142,7 @@ def test_readout_routing_meets_the_tolerance(precision, c3_small):
     routed = (fr & 4) != 0
     print(f"{precision} read-out: routed {routed.sum()} of {routed.size}", flush=True)
     assert sr["n_fp64_fallback"] == routed.sum()
+    assert sr["direct_fp64"] == direct and (routed.all() if direct else True)
     for g in range(s.shape[0] - 1):
         for t in range(1, f):
             z = g * f + t
