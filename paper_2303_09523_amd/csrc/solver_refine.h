@@ -208,14 +208,21 @@ __device__ __forceinline__ void back_substitute(int nb, const PairStore<UPD> (&L
 #pragma unroll
   for (int I = NB - 2; I >= 0; --I) {
     const f32x4 yl = Ls[NB - 1][I / 2].get(I & 1);
-    f32x4 acc;
+    // two accumulators (even and odd K), so that consecutive products do not
+    // wait on each other's MFMA results
+    f32x4 acc, acc2 = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = r >= ne ? yl[v] : 0.0f;
 #pragma unroll
     for (int K = I + 1; K < NB; ++K) {
       const f32x4 P = neg_transpose(Ls[K][I / 2].get(I & 1), buf);
-      acc = acc_qpt(acc, Z[K], P);
+      if ((K - I) & 1)
+        acc = acc_qpt(acc, Z[K], P);
+      else
+        acc2 = acc_qpt(acc2, Z[K], P);
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
     const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
     Z[I] = acc_qpt(z, acc, xs[64 * I + lane]);
   }
@@ -334,6 +341,13 @@ struct MixedTables {
 // LDS read.
 struct MixedSmem : MixedTables {
   double cc64[kConvSize];
+  // Slot of a point in the vector the offset mat-vec reads: the window laid
+  // out 7 wide and 7 high per slice whatever the radius (slots outside the
+  // window stay zero), so the mat-vec's inner loop has a fixed length.
+  __device__ __forceinline__ static int vslot(int d) {
+    const int c = (d >> 8) & 0xff;
+    return (c >> 6) * (kMaxWin * kMaxWin) + ((c >> 3) & 7) * kMaxWin + (c & 7);
+  }
 };
 
 // Leave-one-slice-out blocks also need the pair class (for the derivative
@@ -343,6 +357,7 @@ struct LosoSmem : MixedTables {
   int stride;
   __device__ __forceinline__ const uint8_t* row(int c) const { return cls8 + c * stride; }
   __device__ __forceinline__ double at(const uint8_t* row, int cq) const { return tc64[row[cq]]; }
+  __device__ __forceinline__ static int vslot(int d) { return d & 0x7f; }   // candidate index
 };
 
 __device__ __forceinline__ void mixed_tables(const SolveArgs& a, MixedTables& mt, double tscale) {
@@ -370,9 +385,37 @@ __device__ __forceinline__ void mixed_setup(const SolveArgs& a, const Smem<float
 }
 
 // (C v)_p for the lane's points p = lane, lane + 64, in FP64. v is indexed by
-// candidate (zero for dropped candidates), so the loop runs over the whole
-// window with fixed offsets from each lane's row: no index loads on the way.
-// Offset table: the window's rows of candidates, (dy, dx) in order.
+// MixedSmem::vslot (zero for dropped candidates and for slots outside the
+// window), so the loop runs over the whole 7-wide window rows with fixed
+// offsets from each lane's row: no index loads and no branches inside a row,
+// so a row's table and vector reads are issued together. Slots outside the
+// window add exact zeros. The second point's sums only run when a system has
+// more than 64 points.
+template <bool TWO>
+__device__ __forceinline__ void matvec64_rows(int W, const double* row0, const double* row1,
+                                              const double* vc, double (&a0)[4],
+                                              double (&a1)[4]) {
+  for (int s = 0; s < 2; ++s) {
+    for (int y = 0; y < W; ++y) {
+      const int k = s * kConvSub + y * kConvQ;
+      const double* v = vc + s * (kMaxWin * kMaxWin) + y * kMaxWin;
+      // the row's reads first, then its products
+      double vq[kMaxWin], c0[kMaxWin], c1[kMaxWin];
+#pragma unroll
+      for (int x = 0; x < kMaxWin; ++x) {
+        vq[x] = v[x];
+        c0[x] = row0[k + x];
+        c1[x] = TWO ? row1[k + x] : 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < kMaxWin; ++x) {
+        a0[x & 3] += c0[x] * vq[x];
+        if (TWO) a1[x & 3] += c1[x] * vq[x];
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, const double* vc,
                                          const MixedSmem& ms, double& out0, double& out1) {
   const int lane = threadIdx.x & 63;
@@ -382,21 +425,10 @@ __device__ __forceinline__ void matvec64(int n, int ncand, const int* desc, cons
   int W = 1;
   while (2 * W * W < ncand) ++W;
   double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0};
-  int c = 0;
-  for (int s = 0; s < 2; ++s) {
-    for (int y = 0; y < W; ++y) {
-      const int k = s * kConvSub + y * kConvQ;
-#pragma unroll
-      for (int x = 0; x < kMaxWin; ++x) {
-        if (x < W) {
-          const double vq = vc[c + x];
-          a0[x & 3] += row0[k + x] * vq;
-          a1[x & 3] += row1[k + x] * vq;
-        }
-      }
-      c += W;
-    }
-  }
+  if (n > 64)
+    matvec64_rows<true>(W, row0, row1, vc, a0, a1);
+  else
+    matvec64_rows<false>(W, row0, row1, vc, a0, a1);
   out0 = lane < n ? (a0[0] + a0[1]) + (a0[2] + a0[3]) : 0.0;
   out1 = lane + 64 < n ? (a1[0] + a1[1]) + (a1[2] + a1[3]) : 0.0;
 }
@@ -523,8 +555,8 @@ __device__ __forceinline__ bool mixed_system(int n, int nb, WaveScratch<float>& 
   nuc[lane] = 0.0;
   nuc[lane + 64] = 0.0;
   __builtin_amdgcn_wave_barrier();
-  if (p0 < n) nuc[ws.desc[p0] & 0x7f] = nu0;
-  if (p1 < n) nuc[ws.desc[p1] & 0x7f] = nu1;
+  if (p0 < n) nuc[MS::vslot(ws.desc[p0])] = nu0;
+  if (p1 < n) nuc[MS::vslot(ws.desc[p1])] = nu1;
   __builtin_amdgcn_wave_barrier();
   // ---- 4. FP64 correction ----
   // With h = z' - C nu_w - Q nu_phi (the FP64 residual of the adjoint system)
