@@ -249,8 +249,9 @@ __device__ __forceinline__ void write_rows(const f32x4 (&Z)[NB], int row0, int c
 
 // ---- wave-wide reductions in a fixed order (the results are uniform) ----
 // DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_ror:4 and row_ror:8
-// give every lane its 16-lane row's sum; the four row sums are then read from
-// lanes 0, 16, 32 and 48.
+// give every lane its 16-lane row's sum r0..r3; row_bcast:15 (rows 1 and 3
+// take the last lane of the row before) and row_bcast:31 (rows 2 and 3 take
+// lane 31) then leave (r2 + r3) + (r0 + r1) in lane 63, which is read once.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   const long long b = __double_as_longlong(x);
@@ -262,6 +263,19 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
+// Row broadcasts into the rows of ROWS only; the other rows get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double bcast_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float bcast_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, false));
+}
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
 
 template <int K>
 __device__ __forceinline__ void wave_sums(double (&x)[K]) {
@@ -274,8 +288,11 @@ __device__ __forceinline__ void wave_sums(double (&x)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) x[k] += dpp_d<0x128>(x[k]);
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-    x[k] = (lane_value(x[k], 0) + lane_value(x[k], 16)) + (lane_value(x[k], 32) + lane_value(x[k], 48));
+  for (int k = 0; k < K; ++k) x[k] += bcast_d<kRowBcast15, 0xa>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += bcast_d<kRowBcast31, 0xc>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = lane_value(x[k], 63);
 }
 
 template <int K>
@@ -289,8 +306,11 @@ __device__ __forceinline__ void wave_sums_f(float (&x)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) x[k] += dpp_f<0x128>(x[k]);
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-    x[k] = (lane_value(x[k], 0) + lane_value(x[k], 16)) + (lane_value(x[k], 32) + lane_value(x[k], 48));
+  for (int k = 0; k < K; ++k) x[k] += bcast_f<kRowBcast15, 0xa>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += bcast_f<kRowBcast31, 0xc>(x[k]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = lane_value(x[k], 63);
 }
 
 __device__ __forceinline__ double wave_sum_d(double x) {
