@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  unsigned long long* cursor = &a.ctr->cls_next[NB];
+  ClassRange cr = class_range(a, NB, start, end);
   const int ncand = a.geo.ncand;
   const unsigned plane = (unsigned)a.geo.plane;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -63,10 +63,8 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   const int d1 = lane + 64 < ncand ? sm.sdesc[lane + 64] : 0;
   for (;;) {
     unsigned long long base = 0;
-    if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
-    base = uniform64(base);
-    if (base >= end) break;
-    const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
+    int nk = 0;
+    if (!next_chunk(cr, base, nk)) break;
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
     pipe_prefetch(q, a, 0, d0, d1, below);

@@ -66,7 +66,7 @@ void mixed_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  unsigned long long* cursor = &a.ctr->cls_next[NB];
+  ClassRange cr = class_range(a, NB, start, end);
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
   const double zfloor = 0.01 * (double)__uint_as_float(a.ctr->zmax_bits);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -76,10 +76,8 @@ void mixed_class_kernel(SolveArgs a) {
   unsigned long long refined = 0;
   for (;;) {
     unsigned long long base = 0;
-    if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
-    base = uniform64(base);
-    if (base >= end) break;
-    const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
+    int nk = 0;
+    if (!next_chunk(cr, base, nk)) break;
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
     unsigned sg = 0, sy = 0, sx = 0;

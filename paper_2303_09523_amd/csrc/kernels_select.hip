@@ -50,7 +50,7 @@ __global__ void tables_kernel(Vario v, int f, int r, TableSet t) {
 
 __global__ void reset_kernel(DevCounters* c) {
   int i = threadIdx.x;
-  if (i <= kMaxBlocks) c->cls_next[i] = 0;
+  for (int k = i; k < (kMaxBlocks + 1) * 8; k += blockDim.x) (&c->cls_next[0][0])[k] = 0;
   if (i < kHist) {
     c->hist[i] = 0;
     c->cursor[i] = 0;
@@ -76,7 +76,7 @@ __global__ void reset_kernel(DevCounters* c) {
 
 __global__ void reset_cursors_kernel(DevCounters* c) {
   int i = threadIdx.x;
-  if (i <= kMaxBlocks) c->cls_next[i] = 0;
+  for (int k = i; k < (kMaxBlocks + 1) * 8; k += blockDim.x) (&c->cls_next[0][0])[k] = 0;
   if (i == 0) {
     c->next = 0;
     c->next2 = 0;
@@ -229,12 +229,21 @@ __global__ void scan_kernel(DevCounters* ctr) {
 
 // Each block ranks kScatterPer x 256 systems in an LDS histogram, claims its
 // range of every bucket with one global atomic per bucket, and writes the
-// systems' slots of the size-sorted permutation.
+// systems' slots of the size-sorted permutation. Systems are bucketed by the
+// key of their neighbour count: every count of one size class shares the
+// class's bucket (the full window keeps its own), so within a class the
+// systems keep the order of their columns and neighbouring columns are solved
+// close together in time.
 constexpr int kScatterPer = 16;
+
+struct BucketKeys {
+  uint8_t key[kHist];   // bucket of neighbour count n: the largest n of its class
+};
 
 __global__ __launch_bounds__(256) void scatter_kernel(const uint8_t* __restrict__ count,
                                                       long long nsys, uint32_t* __restrict__ perm,
-                                                      DevCounters* __restrict__ ctr) {
+                                                      DevCounters* __restrict__ ctr,
+                                                      BucketKeys keys) {
   __shared__ unsigned int lh[kHist];
   __shared__ unsigned long long base[kHist];
   const int tid = threadIdx.x;
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint8_t* __restrict_
     nn[k] = 0;
     rank[k] = 0;
     if (sys < nsys) {
-      nn[k] = count[sys] & 0x7f;
+      nn[k] = keys.key[count[sys] & 0x7f];
       rank[k] = atomicAdd(&lh[nn[k]], 1u);
     }
   }
@@ -320,7 +329,8 @@ hipError_t launch_select(const uint8_t* edge, const Geometry& g, const SelectRul
   return launch_select_step(edge, g, 1, g.nslices - 1, rule, bits, count, c, s);
 }
 
-hipError_t launch_bucket(const uint8_t* count, const Geometry& g, uint32_t* perm, DevCounters* c,
+hipError_t launch_bucket(const uint8_t* count, const Geometry& g, int nb, uint32_t* perm,
+                         DevCounters* c,
                          hipStream_t s) {
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(64), 0, s, c);
   hipError_t e = hipGetLastError();
@@ -328,8 +338,17 @@ hipError_t launch_bucket(const uint8_t* count, const Geometry& g, uint32_t* perm
   if (g.nsys < 1) return hipSuccess;
   const long long per = 256ll * kScatterPer;
   const long long blocks = (g.nsys + per - 1) / per;
+  // the size classes of the solve kernels: 16 (NB - 1) - nb < n <= 16 NB - nb
+  BucketKeys keys;
+  for (int n = 0; n < kHist; ++n) {
+    const int NB = (n + nb + 15) / 16;
+    int hi = 16 * NB - nb;
+    if (hi > kHist - 1) hi = kHist - 1;
+    if (n < g.ncand && hi >= g.ncand) hi = g.ncand - 1;
+    keys.key[n] = (uint8_t)(n == g.ncand ? n : hi);
+  }
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, g.nsys, perm,
-                     c);
+                     c, keys);
   return hipGetLastError();
 }
 

@@ -71,7 +71,7 @@ void solve_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  unsigned long long* cursor = &a.ctr->cls_next[NB];
+  ClassRange cr = class_range(a, NB, start, end);
   const T sill = T(a.sill);
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -80,10 +80,8 @@ void solve_class_kernel(SolveArgs a) {
   Tally tally;
   for (;;) {
     unsigned long long base = 0;
-    if (lane == 0) base = start + atomicAdd(cursor, (unsigned long long)kChunk);
-    base = uniform64(base);
-    if (base >= end) break;
-    const int nk = (int)((end - base) < (unsigned long long)kChunk ? (end - base) : kChunk);
+    int nk = 0;
+    if (!next_chunk(cr, base, nk)) break;
     Pipe q;
     pipe_load(q, a, a.perm, base, nk);
     unsigned sg = 0, sy = 0, sx = 0;

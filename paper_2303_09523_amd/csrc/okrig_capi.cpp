@@ -624,7 +624,7 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   }
   {
     PhaseTimer t(p, OKR_PHASE_BUCKET);
-    OKR_HIP(p, okr::launch_bucket(p->count, g, p->perm, p->ctr, strm));
+    OKR_HIP(p, okr::launch_bucket(p->count, g, g.f + 1 + g.drift, p->perm, p->ctr, strm));
   }
   okr::SolveArgs a = solve_args(p, vario);
   a.slices = d_slices;
@@ -1121,7 +1121,7 @@ okr_status okr_loso_forward(okr_plan* p, const okr_variogram* vario, const float
   OKR_HIP(p, okr::launch_tables(vario_of(vario), gl, tables_of(p), p->stream));
   OKR_HIP(p, okr::launch_select_step(d_edge, gl, 2, gl.nslices - 2, p->rule, p->bits, p->count,
                                      p->ctr, p->stream));
-  OKR_HIP(p, okr::launch_bucket(p->count, gl, p->perm, p->ctr, p->stream));
+  OKR_HIP(p, okr::launch_bucket(p->count, gl, gl.f + 1 + gl.drift, p->perm, p->ctr, p->stream));
   okr::SolveArgs a = solve_args(p, vario);
   a.geo = gl;
   a.slices = d_slices;

@@ -65,7 +65,7 @@ struct DevCounters {
   unsigned long long offsets[kHist + 1];  // bucket starts (largest n first)
   unsigned long long cursor[kHist];
   unsigned long long next2;         // second-pass cursor
-  unsigned long long cls_next[kMaxBlocks + 1];  // per size-class cursors
+  unsigned long long cls_next[kMaxBlocks + 1][8];  // per size-class cursors, one per XCD
   unsigned long long n_fallback_list;
 };
 
@@ -78,8 +78,9 @@ hipError_t launch_place(const float* slices, float* volume, float* variance, con
                         DevCounters* c, hipStream_t s);
 hipError_t launch_select(const uint8_t* edge, const Geometry& g, const SelectRule& rule,
                          uint64_t* bits, uint8_t* count, DevCounters* c, hipStream_t s);
-hipError_t launch_bucket(const uint8_t* count, const Geometry& g, uint32_t* perm, DevCounters* c,
-                         hipStream_t s);
+// Size-sorted permutation: buckets by size class (nb border rows), largest first.
+hipError_t launch_bucket(const uint8_t* count, const Geometry& g, int nb, uint32_t* perm,
+                         DevCounters* c, hipStream_t s);
 
 // ---- launchers (kernels_solve.hip) ----
 struct SolveArgs {

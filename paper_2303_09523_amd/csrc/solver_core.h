@@ -833,6 +833,49 @@ __device__ __forceinline__ void block_setup(const SolveArgs& a, Smem<T>& sm, dou
 }
 
 
+// Work ranges by XCD: workgroups are dispatched to the eight XCDs in turn, so
+// the persistent workgroups of one XCD (blockIdx.x modulo the parts) take
+// chunks from their own contiguous part of a size class's range first, and
+// neighbouring columns are solved under one L2; a wave whose part is used up
+// moves on to the next parts, so no XCD idles while another has work. With
+// fewer workgroups than XCDs the range has as many parts as workgroups.
+struct ClassRange {
+  unsigned long long start, len;
+  unsigned long long* cursors;   // one per part
+  unsigned parts, home, visited;
+};
+__device__ __forceinline__ ClassRange class_range(const SolveArgs& a, int NB,
+                                                  unsigned long long start,
+                                                  unsigned long long end) {
+  ClassRange r;
+  r.parts = gridDim.x < 8u ? gridDim.x : 8u;
+  r.home = blockIdx.x % r.parts;
+  r.visited = 0;
+  r.start = start;
+  r.len = end > start ? end - start : 0ull;
+  r.cursors = &a.ctr->cls_next[NB][0];
+  return r;
+}
+// Claims the next chunk of up to kChunk systems: [base, base + nk). Uniform.
+__device__ __forceinline__ bool next_chunk(ClassRange& r, unsigned long long& base, int& nk) {
+  const int lane = threadIdx.x & 63;
+  while (r.visited < r.parts) {
+    const unsigned x = (r.home + r.visited) % r.parts;
+    const unsigned long long lo = r.start + r.len * x / r.parts;
+    const unsigned long long hi = r.start + r.len * (x + 1) / r.parts;
+    unsigned long long b = 0;
+    if (lane == 0) b = lo + atomicAdd(&r.cursors[x], (unsigned long long)kChunk);
+    b = uniform64(b);
+    if (b < hi) {
+      base = b;
+      nk = (int)((hi - b) < (unsigned long long)kChunk ? (hi - b) : kChunk);
+      return true;
+    }
+    ++r.visited;
+  }
+  return false;
+}
+
 // Per-wave tallies of the finished systems, flushed to the counters once per
 // wave (one atomic per wave instead of one per system).
 struct Tally {
