@@ -302,7 +302,11 @@ __global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g
 }
 
 // One thread per full-window system of the size-sorted list (the bucket of
-// n = ncand): gathers its values and applies the cached weights in FP64.
+// n = ncand): gathers its values and applies the cached weights in FP64. The
+// weights sit in LDS in a 7 x 7 layout per slice (zero outside the window), so
+// every window row is one unrolled group of seven loads (slots outside the
+// window reload an in-window value and take a zero weight) instead of a
+// loop of dependent loads.
 __global__ __launch_bounds__(256) void pattern_apply_kernel(const float* __restrict__ slices,
                                                             const uint32_t* __restrict__ perm,
                                                             const DevCounters* __restrict__ ctr,
@@ -311,16 +315,18 @@ __global__ __launch_bounds__(256) void pattern_apply_kernel(const float* __restr
                                                             float* __restrict__ volume,
                                                             float* __restrict__ variance,
                                                             uint8_t* __restrict__ flags) {
-  __shared__ double ws[(kMaxUpsample - 1) * kMaxCand];
+  constexpr int kPad = kMaxWin * kMaxWin;   // slots per slice
+  __shared__ double ws[(kMaxUpsample - 1) * 2 * kPad];
   __shared__ double vs[kMaxUpsample];
-  __shared__ long long off[kMaxCand];
-  const int n = g.ncand, nt = g.f - 1;
-  for (int i = threadIdx.x; i < nt * kMaxCand; i += blockDim.x) ws[i] = W[i];
+  const int n = g.ncand, nt = g.f - 1, Wn = g.W;
+  for (int i = threadIdx.x; i < nt * 2 * kPad; i += blockDim.x) ws[i] = 0.0;
   for (int i = threadIdx.x; i < nt; i += blockDim.x) vs[i] = wvar[i];
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < nt * n; i += blockDim.x) {
+    const int t = i / n, c = i - t * n;
     int dx, dy, s;
     cand_xyz(c, g, &dx, &dy, &s);
-    off[c] = (long long)s * g.plane + (long long)dy * g.nx + dx;
+    ws[t * 2 * kPad + s * kPad + (dy + g.r) * kMaxWin + (dx + g.r)] = W[t * kMaxCand + c];
   }
   __syncthreads();
   const unsigned long long start = ctr->offsets[n];
@@ -333,15 +339,25 @@ __global__ __launch_bounds__(256) void pattern_apply_kernel(const float* __restr
     const int y = (int)(pix / (unsigned)g.nx), x = (int)(pix - (unsigned)y * (unsigned)g.nx);
     // a kept full window lies inside the image; checked, not assumed
     if (x < g.r || y < g.r || x + g.r >= g.nx || y + g.r >= g.ny) continue;
-    const float* base = slices + (long long)gap * g.plane + pix;
+    const float* base = slices + (long long)gap * g.plane + pix - g.r - (long long)g.r * g.nx;
     double acc[kMaxUpsample - 1];
 #pragma unroll
     for (int t = 0; t < kMaxUpsample - 1; ++t) acc[t] = 0.0;
-    for (int c = 0; c < n; ++c) {
-      const double z = base[off[c]];
+    for (int s = 0; s < 2; ++s) {
+      for (int yy = 0; yy < Wn; ++yy) {
+        const float* row = base + (long long)s * g.plane + (long long)yy * g.nx;
+        double z[kMaxWin];
 #pragma unroll
-      for (int t = 0; t < kMaxUpsample - 1; ++t)
-        if (t < nt) acc[t] += ws[t * kMaxCand + c] * z;
+        for (int xx = 0; xx < kMaxWin; ++xx) z[xx] = (double)row[xx < Wn ? xx : Wn - 1];
+        const double* wrow = ws + s * kPad + yy * kMaxWin;
+#pragma unroll
+        for (int t = 0; t < kMaxUpsample - 1; ++t) {
+          if (t < nt) {
+#pragma unroll
+            for (int xx = 0; xx < kMaxWin; ++xx) acc[t] += wrow[t * 2 * kPad + xx] * z[xx];
+          }
+        }
+      }
     }
     for (int t = 0; t < nt; ++t) {
       const long long o = ((long long)gap * g.f + t + 1) * g.plane + pix;
