@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void loso_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  ClassRange cr = class_range(a, NB, start, end);
+  ClassRange cr = class_range(a, NB, start, end, false);
   const int ncand = a.geo.ncand;
   const unsigned plane = (unsigned)a.geo.plane;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));

@@ -66,7 +66,7 @@ void mixed_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  ClassRange cr = class_range(a, NB, start, end);
+  ClassRange cr = class_range(a, NB, start, end, true);
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
   const double zfloor = 0.01 * (double)__uint_as_float(a.ctr->zmax_bits);
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));

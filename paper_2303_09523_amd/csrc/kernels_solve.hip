@@ -71,7 +71,7 @@ void solve_class_kernel(SolveArgs a) {
   if (nlo > nhi) return;
   const unsigned long long start = a.ctr->offsets[nhi];
   const unsigned long long end = a.ctr->offsets[nlo] + a.ctr->hist[nlo];
-  ClassRange cr = class_range(a, NB, start, end);
+  ClassRange cr = class_range(a, NB, start, end, false);
   const T sill = T(a.sill);
   const int ntgt = a.geo.f - 1, ncand = a.geo.ncand;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
