@@ -274,6 +274,50 @@ def edge_postpass_record(w, vol, args, reps: int = 5):
     return rec
 
 
+def loso_record(reps: int = 3):
+    """Leave-one-slice-out loss and adjoint gradient on the 16 x 128^2 field:
+    times from CUDA events over `reps` calls each, and the forward's roofline
+    (algorithmic FLOP of its systems, one held-out target each, against the
+    FP32 MFMA peak of its trailing updates)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2303_09523_amd as P
+    wl = W.workload("loso_16x128")
+    sl_, _ = W.make_inputs(wl)
+    slt = torch.from_numpy(sl_).cuda()
+    pl = P.Plan(wl.m, wl.m, wl.nslices, 2, wl.radius, 4)
+    th = ("exponential", 0.1, 1.0, 2.0)
+    pl.loso_forward(slt, th)
+    pl.loso_backward()
+    hist = np.array(pl.stats()["bucket"], dtype=np.float64)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c2 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(reps):
+        pl.loso_forward(slt, th)
+    c1.record()
+    for _ in range(reps):
+        pl.loso_backward()
+    c2.record()
+    torch.cuda.synchronize()
+    fms, bms = c0.elapsed_time(c1) / reps, c1.elapsed_time(c2) / reps
+    pl.close()
+    nvox = (wl.nslices - 2) * wl.m * wl.m
+    nn = np.arange(len(hist), dtype=np.float64)
+    flops = float((hist * system_flops(nn, 2)).sum())
+    return {"workload": wl.name, "held_out_voxels": nvox, "forward_ms": round(fms, 3),
+            "backward_ms": round(bms, 3),
+            "loss_grad_evals_per_s": round(1000.0 / (fms + bms), 2),
+            "roofline_forward": {
+                "bound": "mfma", "achieved": round(flops / (fms * 1e-3) / 1e12, 3),
+                "peak": PEAKS["fp32_tflops"], "unit": "TFLOP/s",
+                "frac": round(flops / (fms * 1e-3) / 1e12 / PEAKS["fp32_tflops"], 5),
+                "flop": flops, "traffic": None}}
+
+
 TRAFFIC_SOURCES = ["okrig_internal.h", "solver_core.h", "solver_refine.h", "kernels_solve.hip",
                    "kernels_mixed.hip"]
 
@@ -369,6 +413,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the other precisions and the leave-one-slice-out timing")
+    ap.add_argument("--loso-only", action="store_true",
+                    help="only the leave-one-slice-out timing (for profiling its kernels)")
+    ap.add_argument("--pattern-only", action="store_true",
+                    help="only the full-window weight cache plan, profiled per phase")
     ap.add_argument("--edge-only", action="store_true",
                     help="only the edge post-pass on the volume of one untimed execute "
                          "(for profiling its kernels)")
@@ -390,6 +438,28 @@ def main():
     s, e = W.make_inputs(w)
     print(f"# inputs {w.name}: {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
+    if args.loso_only:
+        print(json.dumps({"loso": loso_record(reps=args.steps)}))
+        return
+    if args.pattern_only:
+        import torch
+        import paper_2303_09523_amd as P
+        st = torch.from_numpy(s).cuda()
+        et = torch.from_numpy(e).cuda() if e is not None else None
+        pc = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "pattern",
+                    refine_max=args.refine_max, refine_tol=args.refine_tol)
+        pc.set_profiling(True)
+        vol, var, _ = pc.execute(st, w.vario, et)
+        pc.stats()   # reads and clears the phase clocks of the first execute
+        for _ in range(args.steps):
+            pc.execute(st, w.vario, et, volume=vol, variance=var)
+        sc = pc.stats()
+        pc.close()
+        print(json.dumps({"workload": w.name, "pattern_cache": {
+            "steps": args.steps,
+            "phase_ms_per_step": {k: round(v / args.steps, 3)
+                                  for k, v in sc["phase_ms"].items() if v > 0}}}))
+        return
     if args.edge_only:
         import torch
         import paper_2303_09523_amd as P
@@ -561,20 +631,26 @@ def main():
         pc.execute(st, w.vario, et, volume=vol, variance=var)
         sc = pc.stats()
         pc.close()
-        nfull = int(sc["bucket"][2 * (2 * w.radius + 1) ** 2])
+        ncand = 2 * (2 * w.radius + 1) ** 2
+        nfull = int(sc["bucket"][ncand])
         pat_ms = sc["phase_ms"]["pattern"]
         # algorithmic bytes of a full-window system: its f-1 estimates and variances
-        # written, its column of the two bounding slices read, one list entry
-        pbytes = nfull * (8.0 * (w.upsample - 1) + 8.0 + 4.0)
+        # written, its column of the two bounding slices read, its neighbour count
+        pbytes = nfull * (8.0 * (w.upsample - 1) + 8.0 + 1.0)
+        # algorithmic FLOP: the weighted sums of its f-1 targets over ncand values
+        pflop = nfull * 2.0 * ncand * (w.upsample - 1)
         others["pattern_cache"] = {
             "value": kriged / (mc * 1e-3), "unit": "voxels/s", "ms_per_step": round(mc, 3),
             "dtype": DTYPES[args.precision] + " + f64 cached weights",
             "full_window_systems": nfull, "accuracy": acc_c,
             "phase_ms": {"pattern": round(pat_ms, 3), "solve": round(sc["phase_ms"]["solve"], 3)},
+            # the pattern phase: the weights solve and the stencil apply; the
+            # apply's FP64 FMAs bound it (its HBM bytes take a tenth of the time)
             "roofline_pattern_apply": {
-                "bound": "hbm", "achieved": round(pbytes / (pat_ms * 1e-3) / 1e9, 2),
-                "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                "frac": round(pbytes / (pat_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"], 5),
+                "bound": "alu", "achieved": round(pflop / (pat_ms * 1e-3) / 1e12, 2),
+                "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+                "frac": round(pflop / (pat_ms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], 4),
+                "hbm_gbs": round(pbytes / (pat_ms * 1e-3) / 1e9, 1),
                 "traffic": None}}
         print(f"# pattern cache: {mc:.1f} ms", file=sys.stderr, flush=True)
         # marching cubes on the reconstructed volume (the step after the path)
@@ -607,31 +683,7 @@ def main():
         print(f"# marching cubes: {mesh_ms:.3f} ms, {ntri} triangles", file=sys.stderr,
               flush=True)
         others["edge_postpass"] = edge_postpass_record(w, vol, args)
-        wl = W.workload("loso_16x128")
-        sl_, _ = W.make_inputs(wl)
-        slt = torch.from_numpy(sl_).to(dev)
-        pl = P.Plan(wl.m, wl.m, wl.nslices, 2, wl.radius, 4)
-        th = ("exponential", 0.1, 1.0, 2.0)
-        pl.loso_forward(slt, th)
-        pl.loso_backward()
-        torch.cuda.synchronize()
-        c0 = torch.cuda.Event(enable_timing=True)
-        c1 = torch.cuda.Event(enable_timing=True)
-        c2 = torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(3):
-            pl.loso_forward(slt, th)
-        c1.record()
-        for _ in range(3):
-            pl.loso_backward()
-        c2.record()
-        torch.cuda.synchronize()
-        fms, bms = c0.elapsed_time(c1) / 3, c1.elapsed_time(c2) / 3
-        nvox = (wl.nslices - 2) * wl.m * wl.m
-        loso = {"workload": wl.name, "held_out_voxels": nvox, "forward_ms": round(fms, 3),
-                "backward_ms": round(bms, 3),
-                "loss_grad_evals_per_s": round(1000.0 / (fms + bms), 2)}
-        pl.close()
+        loso = loso_record()
 
     # ---- precision study on the ill-conditioned Gaussian workload ----
     study = None

@@ -62,6 +62,31 @@ __device__ bool chol_lds(double* A, int n) {
   return false;
 }
 
+// The factorisation of chol_lds by a whole workgroup: each step scales the
+// pivot column and then applies every element update of the trailing matrix
+// in one pass, so each element sees the same operations in the same order
+// and the factor is identical. Returns true (uniformly) on a non-positive
+// pivot.
+__device__ bool chol_block(double* A, int n) {
+  for (int k = 0; k < n; ++k) {
+    const double d = A[k * kPtLd + k];
+    if (!(d > 0.0)) return true;
+    const double is = 1.0 / sqrt(d);
+    __syncthreads();   // every thread has read the pivot
+    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x) A[i * kPtLd + k] *= is;
+    if (threadIdx.x == 0) A[k * kPtLd + k] = d * is;   // L[k][k] = sqrt(d)
+    __syncthreads();
+    // rows over waves, the row's columns over lanes
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int i = k + 1 + (int)(threadIdx.x >> 6); i < n; i += nw) {
+      const double lik = A[i * kPtLd + k];
+      for (int j = k + 1 + lane; j <= i; j += 64) A[i * kPtLd + j] -= lik * A[j * kPtLd + k];
+    }
+    __syncthreads();
+  }
+  return false;
+}
+
 // Solves L L^T x = b for two right-hand sides held by rows (b[h] of lane l is
 // row l + 64 h); on return b holds x.
 __device__ void subst_lds(const double* A, int n, double (&b)[2], double (&c)[2]) {
@@ -219,30 +244,30 @@ __device__ __forceinline__ void cand_xyz(int c, const Geometry& g, int* dx, int*
   *dx = o - (o / g.W) * g.W - g.r;
 }
 
-__global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g, double* W,
-                                                             double* wvar, DevCounters* ctr) {
+__global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry g, double* W,
+                                                               double* wvar, DevCounters* ctr) {
   __shared__ double A[kPtMax * kPtLd];
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int n = g.ncand;
-  for (int i = lane; i < n; i += 64) {
-    int dxi, dyi, si;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - (e / n) * n;
+    if (j > i) continue;
+    int dxi, dyi, si, dxj, dyj, sj;
     cand_xyz(i, g, &dxi, &dyi, &si);
-    for (int j = 0; j <= i; ++j) {
-      int dxj, dyj, sj;
-      cand_xyz(j, g, &dxj, &dyj, &sj);
-      const double ddx = dxi - dxj, ddy = dyi - dyj, ddz = (double)(si - sj) * g.f;
-      A[i * kPtLd + j] = i == j ? v.sill : cov_d(v, sqrt(ddx * ddx + ddy * ddy + ddz * ddz));
-    }
+    cand_xyz(j, g, &dxj, &dyj, &sj);
+    const double ddx = dxi - dxj, ddy = dyi - dyj, ddz = (double)(si - sj) * g.f;
+    A[i * kPtLd + j] = i == j ? v.sill : cov_d(v, sqrt(ddx * ddx + ddy * ddy + ddz * ddz));
   }
-  __builtin_amdgcn_wave_barrier();
-  if (chol_lds(A, n)) {
-    if (lane == 0) atomicAdd(&ctr->bad_pivot, 1ull);
+  __syncthreads();
+  if (chol_block(A, n)) {
+    if (threadIdx.x == 0) atomicAdd(&ctr->bad_pivot, 1ull);
     for (int t = 0; t < g.f - 1; ++t) {
-      for (int i = lane; i < n; i += 64) W[t * kMaxCand + i] = __builtin_nan("");
-      if (lane == 0) wvar[t] = __builtin_nan("");
+      for (int i = threadIdx.x; i < n; i += blockDim.x) W[t * kMaxCand + i] = __builtin_nan("");
+      if (threadIdx.x == 0) wvar[t] = __builtin_nan("");
     }
     return;
   }
+  // each wave solves the targets t = 1 + wid (mod waves) against the shared factor
   // slice of each candidate (0 lower, 1 upper) and, with the drift, X_s = C^-1 s
   double sl[2], xs[2] = {0.0, 0.0};
 #pragma unroll
@@ -258,7 +283,7 @@ __global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g
     xs[1] = sl[1];
     subst_lds(A, n, xs, unused);
   }
-  for (int t = 1; t < g.f; ++t) {
+  for (int t = 1 + wid; t < g.f; t += blockDim.x >> 6) {
     double b1[2], bc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -301,70 +326,139 @@ __global__ __launch_bounds__(64) void pattern_weights_kernel(Vario v, Geometry g
   }
 }
 
-// One thread per full-window system of the size-sorted list (the bucket of
-// n = ncand): gathers its values and applies the cached weights in FP64. The
-// weights sit in LDS in a 7 x 7 layout per slice (zero outside the window), so
-// every window row is one unrolled group of seven loads (slots outside the
-// window reload an in-window value and take a zero weight) instead of a
-// loop of dependent loads.
-__global__ __launch_bounds__(256) void pattern_apply_kernel(const float* __restrict__ slices,
-                                                            const uint32_t* __restrict__ perm,
-                                                            const DevCounters* __restrict__ ctr,
+// The full-window systems apply the cached weights as a stencil. A workgroup
+// of 64 x 4 threads covers a 64 x 16 tile of one gap: both bounding slices of
+// the tile and its window halo are staged once in LDS, converted to FP64, with
+// coalesced row loads. Each thread computes a column of kRows pixels, window
+// row by window row: the staged rows its pixels need at one window row are the
+// rows of the previous window row shifted by one, so each step reads one new
+// row from LDS and the rest stay in registers; the weights of a window row are
+// wave-uniform (scalar loads, an FMA operand each), so LDS serves only the
+// slice values. A pixel's sum runs over slice, window row, window column for
+// each target in turn, the order of the per-system FP64 weighted sum; its
+// result is stored when its kept window is the full window (count = ncand).
+// Targets go in groups of three (the weights of a group's missing targets
+// repeat the last one and are not stored).
+constexpr int kPTX = 64, kRows = 4, kPTY = 4 * kRows, kTGroup = 3;
+
+template <int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void pattern_apply_kernel(const float* __restrict__ slices,
+                                                            const uint8_t* __restrict__ count,
                                                             Geometry g, const double* __restrict__ W,
                                                             const double* __restrict__ wvar,
                                                             float* __restrict__ volume,
                                                             float* __restrict__ variance,
                                                             uint8_t* __restrict__ flags) {
-  constexpr int kPad = kMaxWin * kMaxWin;   // slots per slice
-  __shared__ double ws[(kMaxUpsample - 1) * 2 * kPad];
-  __shared__ double vs[kMaxUpsample];
-  const int n = g.ncand, nt = g.f - 1, Wn = g.W;
-  for (int i = threadIdx.x; i < nt * 2 * kPad; i += blockDim.x) ws[i] = 0.0;
-  for (int i = threadIdx.x; i < nt; i += blockDim.x) vs[i] = wvar[i];
-  __syncthreads();
-  for (int i = threadIdx.x; i < nt * n; i += blockDim.x) {
-    const int t = i / n, c = i - t * n;
-    int dx, dy, s;
-    cand_xyz(c, g, &dx, &dy, &s);
-    ws[t * 2 * kPad + s * kPad + (dy + g.r) * kMaxWin + (dx + g.r)] = W[t * kMaxCand + c];
+  constexpr int Wn = 2 * R + 1, W2 = Wn * Wn;
+  constexpr int kTX = kPTX + 2 * R, kTY = kPTY + 2 * R;
+  __shared__ double tile[2][kTY][kTX];
+  const int n = g.ncand, nt = g.f - 1;
+  const int gap = blockIdx.z, x0 = blockIdx.x * kPTX, y0 = blockIdx.y * kPTY;
+  const int lx = threadIdx.x & (kPTX - 1), ly0 = (threadIdx.x / kPTX) * kRows;
+  const int x = x0 + lx;
+  // The loads below are unconditional, from coordinates clamped into the
+  // image (values from outside are replaced or unused), so that every load of
+  // a thread is in flight before the first is used: first the neighbour counts
+  // of the thread's pixels, then its share of the tile,
+  // tile[s][ty][tx] = slice gap + s at (y0 - R + ty, x0 - R + tx), 0 outside.
+  uint8_t cn[kRows];
+#pragma unroll
+  for (int p = 0; p < kRows; ++p)
+    cn[p] = count[(long long)gap * g.plane + (long long)min(y0 + ly0 + p, g.ny - 1) * g.nx +
+                  min(x, g.nx - 1)];
+  constexpr int kStage = (2 * kTY * kTX + 255) / 256;
+  float sv[kStage];
+  bool in[kStage];
+#pragma unroll
+  for (int it = 0; it < kStage; ++it) {
+    const int i = min((int)threadIdx.x + 256 * it, 2 * kTY * kTX - 1);
+    const int sl = i / (kTY * kTX), rem = i - sl * (kTY * kTX);
+    const int ty = rem / kTX, tx = rem - ty * kTX;
+    const int yy = y0 - R + ty, xx = x0 - R + tx;
+    in[it] = yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx;
+    const int yc = min(max(yy, 0), g.ny - 1), xc = min(max(xx, 0), g.nx - 1);
+    sv[it] = slices[(long long)(gap + sl) * g.plane + (long long)yc * g.nx + xc];
+  }
+#pragma unroll
+  for (int it = 0; it < kStage; ++it) {
+    const int i = threadIdx.x + 256 * it;
+    if (i < 2 * kTY * kTX) (&tile[0][0][0])[i] = in[it] ? (double)sv[it] : 0.0;
   }
   __syncthreads();
-  const unsigned long long start = ctr->offsets[n];
-  const unsigned long long cnt = ctr->hist[n];
-  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < cnt;
-       i += (unsigned long long)gridDim.x * blockDim.x) {
-    const unsigned sys = perm[start + i];
-    const unsigned gap = sys / (unsigned)g.plane;
-    const unsigned pix = sys - gap * (unsigned)g.plane;
-    const int y = (int)(pix / (unsigned)g.nx), x = (int)(pix - (unsigned)y * (unsigned)g.nx);
-    // a kept full window lies inside the image; checked, not assumed
-    if (x < g.r || y < g.r || x + g.r >= g.nx || y + g.r >= g.ny) continue;
-    const float* base = slices + (long long)gap * g.plane + pix - g.r - (long long)g.r * g.nx;
-    double acc[kMaxUpsample - 1];
+  if (x >= g.nx) return;
+  // which of the thread's pixels take the cached weights
+  unsigned keep = 0;
 #pragma unroll
-    for (int t = 0; t < kMaxUpsample - 1; ++t) acc[t] = 0.0;
-    for (int s = 0; s < 2; ++s) {
+  for (int p = 0; p < kRows; ++p) {
+    const int y = y0 + ly0 + p;
+    if (y < g.ny && x >= R && y >= R && x + R < g.nx && y + R < g.ny && (cn[p] & 0x7f) == n)
+      keep |= 1u << p;
+  }
+  if (!keep) return;
+  for (int t0 = 0; t0 < nt; t0 += kTGroup) {
+    const double* w[kTGroup];
+#pragma unroll
+    for (int t = 0; t < kTGroup; ++t) w[t] = W + (long long)min(t0 + t, nt - 1) * kMaxCand;
+    double acc[kRows][kTGroup];
+#pragma unroll
+    for (int p = 0; p < kRows; ++p)
+#pragma unroll
+      for (int t = 0; t < kTGroup; ++t) acc[p][t] = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      double z[kRows][Wn];   // z[(p + yy) % kRows]: staged row ly0 + p + yy
+#pragma unroll
+      for (int q = 0; q < kRows - 1; ++q)
+#pragma unroll
+        for (int xx = 0; xx < Wn; ++xx) z[q][xx] = tile[sl][ly0 + q][lx + xx];
+#pragma unroll
       for (int yy = 0; yy < Wn; ++yy) {
-        const float* row = base + (long long)s * g.plane + (long long)yy * g.nx;
-        double z[kMaxWin];
+        // The weights of this window row (3 x W doubles in SGPRs). An opaque
+        // row offset and a scheduling barrier keep each row's loads in its
+        // step: the 2 x W x W x 3 weights do not fit in SGPRs.
+        __builtin_amdgcn_sched_barrier(0);
+        int off = (sl * Wn + yy) * Wn;   // slot sl * W2 + yy * Wn
+        asm volatile("" : "+s"(off));
+        double wr[kTGroup][Wn];
 #pragma unroll
-        for (int xx = 0; xx < kMaxWin; ++xx) z[xx] = (double)row[xx < Wn ? xx : Wn - 1];
-        const double* wrow = ws + s * kPad + yy * kMaxWin;
+        for (int t = 0; t < kTGroup; ++t)
 #pragma unroll
-        for (int t = 0; t < kMaxUpsample - 1; ++t) {
-          if (t < nt) {
+          for (int xx = 0; xx < Wn; ++xx) wr[t][xx] = w[t][off + xx];
+        const int qn = (yy + kRows - 1) % kRows;   // row ly0 + kRows - 1 + yy
 #pragma unroll
-            for (int xx = 0; xx < kMaxWin; ++xx) acc[t] += wrow[t * 2 * kPad + xx] * z[xx];
-          }
-        }
+        for (int xx = 0; xx < Wn; ++xx) z[qn][xx] = tile[sl][ly0 + kRows - 1 + yy][lx + xx];
+#pragma unroll
+        for (int t = 0; t < kTGroup; ++t)
+#pragma unroll
+          for (int xx = 0; xx < Wn; ++xx)
+#pragma unroll
+            for (int p = 0; p < kRows; ++p)
+              acc[p][t] = fma(wr[t][xx], z[(p + yy) % kRows][xx], acc[p][t]);
       }
     }
-    for (int t = 0; t < nt; ++t) {
-      const long long o = ((long long)gap * g.f + t + 1) * g.plane + pix;
-      volume[o] = (float)acc[t];
-      if (variance) variance[o] = (float)vs[t];
+    // pinned here: otherwise each pixel's sums sink into its conditional
+    // store, and every window row's weights stay live until then
+#pragma unroll
+    for (int p = 0; p < kRows; ++p)
+#pragma unroll
+      for (int t = 0; t < kTGroup; ++t) asm volatile("" : "+v"(acc[p][t]));
+#pragma unroll
+    for (int p = 0; p < kRows; ++p) {
+      if (!(keep >> p & 1u)) continue;
+      const long long pix = (long long)(y0 + ly0 + p) * g.nx + x;
+#pragma unroll
+      for (int t = 0; t < kTGroup; ++t) {
+        if (t0 + t >= nt) break;
+        const long long o = ((long long)gap * g.f + t0 + t + 1) * g.plane + pix;
+        volume[o] = (float)acc[p][t];
+        if (variance) variance[o] = (float)wvar[t0 + t];
+      }
     }
-    if (flags) flags[sys] = 0;
+  }
+  if (flags) {
+#pragma unroll
+    for (int p = 0; p < kRows; ++p)
+      if (keep >> p & 1u) flags[(long long)gap * g.plane + (long long)(y0 + ly0 + p) * g.nx + x] = 0;
   }
 }
 
@@ -385,14 +479,28 @@ hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
 
 namespace okr {
 
-hipError_t launch_pattern(const float* slices, const uint32_t* perm, DevCounters* c,
+hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
                           const Geometry& g, const Vario& v, double* W, double* wvar,
-                          float* volume, float* variance, uint8_t* flags, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(64), 0, s, v, g, W, wvar, c);
+                          float* volume, float* variance, uint8_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(1024), 0, s, v, g, W, wvar, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pattern_apply_kernel, dim3(grid), dim3(256), 0, s, slices, perm, c, g, W,
-                     wvar, volume, variance, flags);
+  if (g.nslices < 2) return hipSuccess;
+  dim3 grid((g.nx + kPTX - 1) / kPTX, (g.ny + kPTY - 1) / kPTY, g.nslices - 1);
+  switch (g.r) {
+#define OKR_PATTERN_R(RR)                                                                      \
+  case RR:                                                                                     \
+    hipLaunchKernelGGL(pattern_apply_kernel<RR>, grid, dim3(256), 0, s, slices, count, g, W,   \
+                       wvar, volume, variance, flags);                                         \
+    break;
+    OKR_PATTERN_R(0)
+    OKR_PATTERN_R(1)
+    OKR_PATTERN_R(2)
+    OKR_PATTERN_R(3)
+#undef OKR_PATTERN_R
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

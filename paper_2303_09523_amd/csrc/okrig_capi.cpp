@@ -634,9 +634,9 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   if (p->prob.algo == OKR_ALGO_PATTERN_CACHE) {
     // the full-window systems from the cached FP64 weights; the rest below
     PhaseTimer t(p, OKR_PHASE_PATTERN);
-    OKR_HIP(p, okr::launch_pattern(d_slices, p->perm, p->ctr, g, vario_of(vario), p->pattern_w,
+    OKR_HIP(p, okr::launch_pattern(d_slices, p->count, p->ctr, g, vario_of(vario), p->pattern_w,
                                    p->pattern_w + (okr::kMaxUpsample - 1) * okr::kMaxCand,
-                                   d_volume, d_variance, d_flags, p->num_cu * 8, strm));
+                                   d_volume, d_variance, d_flags, strm));
     a.nmax = g.ncand - 1;
   }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;

@@ -122,9 +122,9 @@ int solve_blocks_needed(const Geometry& g);
 hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
 
 // ---- launchers (kernels_points.hip) ----
-hipError_t launch_pattern(const float* slices, const uint32_t* perm, DevCounters* c,
+hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
                           const Geometry& g, const Vario& v, double* W, double* wvar,
-                          float* volume, float* variance, uint8_t* flags, int grid, hipStream_t s);
+                          float* volume, float* variance, uint8_t* flags, hipStream_t s);
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
                          const int64_t* offset, const float* xyz, const float* val,
                          const float* txyz, float* est, float* var, float* weights,

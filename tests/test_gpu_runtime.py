@@ -111,3 +111,29 @@ def test_autotune_keeps_results():
     kz[::f] = False
     assert rel_err_est(vn[kz], vo[kz], np.abs(s).max()).max() <= 1e-5
     plan.close()
+
+
+def test_allocation_failures_are_reported(monkeypatch):
+    """A forced device allocation failure (OKR_FAIL_ALLOC) makes plan creation
+    and the lazily allocated leave-one-slice-out workspace return OKR_E_OOM
+    with nothing left half-built; the same calls succeed once it is lifted."""
+    import torch
+    import paper_2303_09523_amd as P
+    s, e = _inputs()
+    n, ny, nx = s.shape
+    monkeypatch.setenv("OKR_FAIL_ALLOC", "1")
+    with pytest.raises(P.OkrError) as ei:
+        P.Plan(nx, ny, n, 4, 3)
+    assert ei.value.status == 5
+    monkeypatch.delenv("OKR_FAIL_ALLOC")
+    plan = P.Plan(nx, ny, n, 2, 2)
+    st = torch.from_numpy(s).cuda()
+    monkeypatch.setenv("OKR_FAIL_ALLOC", "1")
+    with pytest.raises(P.OkrError) as ei:
+        plan.loso_forward(st, ("exponential", 0.1, 1.0, 2.0))
+    assert ei.value.status == 5
+    monkeypatch.delenv("OKR_FAIL_ALLOC")
+    loss = plan.loso_forward(st, ("exponential", 0.1, 1.0, 2.0))
+    grad = plan.loso_backward()
+    plan.close()
+    assert np.isfinite(float(loss)) and torch.isfinite(grad).all()
