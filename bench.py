@@ -274,6 +274,51 @@ def edge_postpass_record(w, vol, args, reps: int = 5):
     return rec
 
 
+def mcubes_record(w, s, vol, args, reps: int = 5):
+    """Marching cubes of the reconstructed volume at the median of the known
+    slices: library HIP-event time per call and the HBM roofline."""
+    import numpy as np
+    import paper_2303_09523_amd as P
+    pm = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
+                refine_max=args.refine_max)
+    iso = float(np.median(s))
+    tris, ids = pm.marching_cubes(vol, iso)
+    ntri = int(tris.shape[0])
+    pm.set_profiling(True)
+    for _ in range(reps):
+        pm.marching_cubes(vol, iso, max_tris=ntri)
+    smc = pm.stats()
+    pm.close()
+    mesh_ms = smc["phase_ms"]["mesh"] / max(1, smc["phase_calls"]["mesh"])
+    nz, ny, nx = vol.shape
+    ncubes = (nz - 1) * (ny - 1) * (nx - 1)
+    # algorithmic bytes: the volume read once, each triangle's vertices and cube id written
+    mbytes = 4.0 * nz * ny * nx + 44.0 * ntri
+    del tris, ids
+    print(f"# marching cubes: {mesh_ms:.3f} ms, {ntri} triangles", file=sys.stderr, flush=True)
+    return {
+        "value": ncubes / (mesh_ms * 1e-3), "unit": "cubes/s", "ms": round(mesh_ms, 4),
+        "cubes": ncubes, "triangles": ntri, "iso": iso,
+        "timing": "library HIP events around the count, scan and emit launches",
+        "roofline": {
+            "bound": "hbm", "achieved": round(mbytes / (mesh_ms * 1e-3) / 1e9, 2),
+            "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+            "frac": round(mbytes / (mesh_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"], 5),
+            "traffic": mesh_traffic_from_profiles(args.workload)}}
+
+
+def _calibration_copy(nbytes):
+    """A plain device copy of nbytes, whose FETCH_SIZE / WRITE_SIZE scale the
+    counters of the kernels of the same run."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"copy_bytes": int(src.numel() * 4)}
+
+
 def loso_record(reps: int = 3):
     """Leave-one-slice-out loss and adjoint gradient on the 16 x 128^2 field:
     times from CUDA events over `reps` calls each, and the forward's roofline
@@ -417,6 +462,8 @@ def main():
                     help="only the leave-one-slice-out timing (for profiling its kernels)")
     ap.add_argument("--pattern-only", action="store_true",
                     help="only the full-window weight cache plan, profiled per phase")
+    ap.add_argument("--mcubes-only", action="store_true",
+                    help="only marching cubes on the reconstructed volume")
     ap.add_argument("--edge-only", action="store_true",
                     help="only the edge post-pass on the volume of one untimed execute "
                          "(for profiling its kernels)")
@@ -455,12 +502,16 @@ def main():
             pc.execute(st, w.vario, et, volume=vol, variance=var)
         sc = pc.stats()
         pc.close()
-        print(json.dumps({"workload": w.name, "pattern_cache": {
+        rec = {"workload": w.name, "pattern_cache": {
             "steps": args.steps,
+            "full_window_systems": int(sc["bucket"][2 * (2 * w.radius + 1) ** 2]),
             "phase_ms_per_step": {k: round(v / args.steps, 3)
-                                  for k, v in sc["phase_ms"].items() if v > 0}}}))
+                                  for k, v in sc["phase_ms"].items() if v > 0}}}
+        if args.calib_copy > 0:
+            rec["calibration"] = _calibration_copy(args.calib_copy)
+        print(json.dumps(rec))
         return
-    if args.edge_only:
+    if args.edge_only or args.mcubes_only:
         import torch
         import paper_2303_09523_amd as P
         st = torch.from_numpy(s).cuda()
@@ -469,15 +520,13 @@ def main():
                     refine_max=args.refine_max, refine_tol=args.refine_tol)
         vol, _, _ = pk.execute(st, w.vario, et)
         pk.close()
-        rec = edge_postpass_record(w, vol, args, reps=args.steps)
+        if args.edge_only:
+            rec = {"edge_postpass": edge_postpass_record(w, vol, args, reps=args.steps)}
+        else:
+            rec = {"marching_cubes": mcubes_record(w, s, vol, args, reps=args.steps)}
         if args.calib_copy > 0:
-            src = torch.empty(args.calib_copy // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-            dst = torch.empty_like(src)
-            torch.cuda.synchronize()
-            dst.copy_(src)
-            torch.cuda.synchronize()
-            rec["calibration"] = {"copy_bytes": int(src.numel() * 4)}
-        print(json.dumps({"workload": w.name, "edge_postpass": rec}))
+            rec["calibration"] = _calibration_copy(args.calib_copy)
+        print(json.dumps({"workload": w.name, **rec}))
         return
 
     cpu = None
@@ -591,13 +640,7 @@ def main():
 
     calib = None
     if args.calib_copy > 0:
-        src = torch.empty(args.calib_copy // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        calib = {"copy_bytes": int(src.numel() * 4)}
-        del src, dst
+        calib = _calibration_copy(args.calib_copy)
 
     # ---- the other operating points of the batched path ----
     others = {}
@@ -653,35 +696,7 @@ def main():
                 "hbm_gbs": round(pbytes / (pat_ms * 1e-3) / 1e9, 1),
                 "traffic": None}}
         print(f"# pattern cache: {mc:.1f} ms", file=sys.stderr, flush=True)
-        # marching cubes on the reconstructed volume (the step after the path)
-        pm = P.Plan(w.m, w.m, w.nslices, w.upsample, w.radius, 4, args.precision, "batched",
-                    refine_max=args.refine_max)
-        iso = float(np.median(s))
-        tris, ids = pm.marching_cubes(vol, iso)
-        ntri = int(tris.shape[0])
-        pm.set_profiling(True)
-        reps = 5
-        for _ in range(reps):
-            pm.marching_cubes(vol, iso, max_tris=ntri)
-        smc = pm.stats()
-        pm.close()
-        mesh_ms = smc["phase_ms"]["mesh"] / max(1, smc["phase_calls"]["mesh"])
-        nz, ny, nx = vol.shape
-        ncubes = (nz - 1) * (ny - 1) * (nx - 1)
-        # algorithmic bytes: the volume read once, each triangle's vertices and cube id written
-        mbytes = 4.0 * nz * ny * nx + 44.0 * ntri
-        others["marching_cubes"] = {
-            "value": ncubes / (mesh_ms * 1e-3), "unit": "cubes/s", "ms": round(mesh_ms, 4),
-            "cubes": ncubes, "triangles": ntri, "iso": iso,
-            "timing": "library HIP events around the count, scan and emit launches",
-            "roofline": {
-                "bound": "hbm", "achieved": round(mbytes / (mesh_ms * 1e-3) / 1e9, 2),
-                "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                "frac": round(mbytes / (mesh_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"], 5),
-                "traffic": mesh_traffic_from_profiles(args.workload)}}
-        del tris, ids
-        print(f"# marching cubes: {mesh_ms:.3f} ms, {ntri} triangles", file=sys.stderr,
-              flush=True)
+        others["marching_cubes"] = mcubes_record(w, s, vol, args)
         others["edge_postpass"] = edge_postpass_record(w, vol, args)
         loso = loso_record()
 
