@@ -86,8 +86,11 @@ typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 
  * PATTERN_CACHE: BATCHED, except that the systems keeping the whole window
  * (the same matrix for all of them, by translation invariance) take weights
  * and variances computed once per launch in FP64 and applied as FP64 dot
- * products; the other systems are solved as in BATCHED at the plan's
- * precision. */
+ * products, and, without the slice predictor, the systems of the size
+ * classes that drop at most 32 candidates of the window take theirs from the
+ * window's FP64 inverse (the block-inverse identity, one k x k solve per
+ * system for its k dropped candidates); the other systems are solved as in
+ * BATCHED at the plan's precision. */
 typedef enum { OKR_ALGO_BATCHED = 0, OKR_ALGO_PLAIN_PER_VOXEL = 1,
                OKR_ALGO_PATTERN_CACHE = 2 } okr_algo;
 
@@ -173,7 +176,8 @@ typedef struct {
                                  last okr_stats_get: 0 placement, 1 tables, 2 selection,
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
                                  6 plain per-voxel kernel, 7 leave-one-slice-out,
-                                 8 full-window pattern weights + application,
+                                 8 full-window pattern weights + application
+                                 (and the systems served from the window's inverse),
                                  9 marching cubes, edge post-pass: 10 shearlet
                                  coefficients, 11 edge thinning, 12 chain tracing and
                                  re-routing (with the copy of the input to the output) */
@@ -355,7 +359,7 @@ okr_status okr_plan_destroy(okr_plan* plan);
  * loops, harnesses that forbid hipMalloc. Same arguments and results as
  * okr_plan_create + okr_execute on the given problem (identical kernels;
  * the launch shape is the untuned default and no graph is used), except:
- *   - the workspace is a static device array of the library, 26.2 MB per GPU
+ *   - the workspace is a static device array of the library, 26.4 MB per GPU
  *     it runs on, held until the process ends: problems of at most 2^20
  *     (column, gap) systems ((nslices-1)*nx*ny <= 1048576), larger ones get
  *     OKR_E_SHAPE before any device work;

@@ -12,6 +12,8 @@
 // running over rows. Invalid counts and non-finite inputs are latched in the
 // counters and reported at the next synchronising call; a non-positive pivot
 // gives NaN outputs for that system and is counted.
+#include <algorithm>
+
 #include "okrig_internal.h"
 #include "variogram.h"
 
@@ -244,9 +246,14 @@ __device__ __forceinline__ void cand_xyz(int c, const Geometry& g, int* dx, int*
   *dx = o - (o / g.W) * g.W - g.r;
 }
 
-__global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry g, double* W,
-                                                               double* wvar, DevCounters* ctr) {
+__global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry g, double* pat,
+                                                               DevCounters* ctr) {
   __shared__ double A[kPtMax * kPtLd];
+  double* W = pat + kPatW;
+  double* wvar = pat + kPatVar;
+  double* G = pat + kPatG;
+  double* U = pat + kPatU;
+  double* C0 = pat + kPatC0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int n = g.ncand;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -265,7 +272,29 @@ __global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry
       for (int i = threadIdx.x; i < n; i += blockDim.x) W[t * kMaxCand + i] = __builtin_nan("");
       if (threadIdx.x == 0) wvar[t] = __builtin_nan("");
     }
+    for (int i = threadIdx.x; i < kMaxCand * kMaxCand; i += blockDim.x) G[i] = __builtin_nan("");
+    for (int i = threadIdx.x; i < kMaxUpsample * kMaxCand; i += blockDim.x) U[i] = __builtin_nan("");
     return;
+  }
+  // G = C^{-1}, two columns per solve (rows by symmetry: row c of G is C^{-1} e_c)
+  for (int c = 2 * wid; c < n; c += 2 * (int)(blockDim.x >> 6)) {
+    double e0[2], e1[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      e0[h] = i == c ? 1.0 : 0.0;
+      e1[h] = i == c + 1 ? 1.0 : 0.0;
+    }
+    subst_lds(A, n, e0, e1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i < n) {
+        G[c * kMaxCand + i] = e0[h];
+        if (c + 1 < n) G[(c + 1) * kMaxCand + i] = e1[h];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   // each wave solves the targets t = 1 + wid (mod waves) against the shared factor
   // slice of each candidate (0 lower, 1 upper) and, with the drift, X_s = C^-1 s
@@ -299,6 +328,17 @@ __global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry
     }
     const double c0[2] = {bc[0], bc[1]};
     subst_lds(A, n, b1, bc);
+    // the full-window solves C^{-1} 1 and C^{-1} c0_t, and c0_t, for the
+    // systems that take their weights from G
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i < n) {
+        if (t == 1) U[i] = b1[h];
+        U[t * kMaxCand + i] = bc[h];
+        C0[(t - 1) * kMaxCand + i] = c0[h];
+      }
+    }
     const double s1 = wave_sum(b1[0] + b1[1]);
     const double sc = wave_sum(bc[0] + bc[1]);
     double w0, w1, lagr;
@@ -462,6 +502,215 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
   }
 }
 
+// Systems that keep all but k <= kMaxDrop candidates of the full window
+// (drop set D, kept set K) take their weights from the full window's inverse
+// G = C^{-1} and its solves u_r = G b_r (b_0 = 1, b_t = c0_t): by the block
+// inverse of C, C_KK^{-1} = G_KK - G_KD G_DD^{-1} G_DK, and since
+// u_D = G_DK b_K + G_DD b_D,
+//   x_r = C_KK^{-1} b_K = u_K - G_KD y_r,   G_DD y_r = u_D,
+// exactly (up to rounding) and whatever b holds at the dropped candidates.
+// Per system one wave: the k x k matrix G_DD is gathered into LDS and
+// factored (lanes over rows), the k-vectors y_r are solved with lanes over
+// rows, and x_r for the kept candidates (two per lane) follow from rows of G.
+// Then mu_t = (1'x_t - 1) / 1'x_0, w_t = x_t - mu_t x_0, the estimate w_t'z
+// and the variance sill - w_t'c0_t - mu_t, all in FP64. Targets go in groups
+// of three (x_0 solved again for each group).
+struct DowndateScratch {
+  double a[kMaxDrop][kMaxDrop + 1];   // G_DD, then its Cholesky factor (lower triangle)
+  int dl[kMaxDrop];                   // the dropped candidates, ascending
+};
+constexpr int kDdWaves = 4;
+
+__global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4))) void pattern_downdate_kernel(
+    const float* __restrict__ slices, const uint64_t* __restrict__ bits,
+    const uint8_t* __restrict__ count, const uint32_t* __restrict__ perm,
+    DevCounters* __restrict__ ctr, Geometry g, double sill, const double* __restrict__ pat,
+    int nlo, float* __restrict__ volume, float* __restrict__ variance,
+    uint8_t* __restrict__ flags) {
+  __shared__ DowndateScratch wsa[kDdWaves];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  DowndateScratch& ws = wsa[wid];
+  const double* G = pat + kPatG;
+  const double* U = pat + kPatU;
+  const double* C0 = pat + kPatC0;
+  const int nc = g.ncand, nt = g.f - 1;
+  const unsigned long long start = ctr->offsets[nc - 1];
+  const unsigned long long end = ctr->offsets[nlo] + ctr->hist[nlo];
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  // the lane's two candidates: in range, and their offset in the slice stack
+  const bool in0 = lane < nc, in1 = lane + 64 < nc;
+  long long off0 = 0, off1 = 0;
+  int dy0 = 0, dx0 = 0, dy1 = 0, dx1 = 0;
+  {
+    int s;
+    if (in0) {
+      cand_xyz(lane, g, &dx0, &dy0, &s);
+      off0 = (long long)s * g.plane + (long long)dy0 * g.nx + dx0;
+    }
+    if (in1) {
+      cand_xyz(lane + 64, g, &dx1, &dy1, &s);
+      off1 = (long long)s * g.plane + (long long)dy1 * g.nx + dx1;
+    }
+  }
+  for (unsigned long long it = start + (unsigned long long)blockIdx.x * kDdWaves + wid; it < end;
+       it += (unsigned long long)gridDim.x * kDdWaves) {
+    const unsigned sys = __builtin_amdgcn_readfirstlane(perm[it]);
+    const int k = nc - (count[sys] & 0x7f);
+    if (k < 1 || k > kMaxDrop) continue;   // not a system of this range
+    const uint64_t lo = bits[2ull * sys], hi = bits[2ull * sys + 1];
+    const bool keep0 = in0 && ((lo >> lane) & 1ull);
+    const bool keep1 = in1 && ((hi >> lane) & 1ull);
+    const uint64_t m0 = __ballot(in0 && !keep0), m1 = __ballot(in1 && !keep1);
+    if (__popcll(m0) + __popcll(m1) != k) continue;   // count and mask disagree: not ours
+    if (in0 && !keep0) ws.dl[__popcll(m0 & below)] = lane;
+    if (in1 && !keep1) ws.dl[__popcll(m0) + __popcll(m1 & below)] = lane + 64;
+    __builtin_amdgcn_wave_barrier();
+    // G_DD, lower triangle (two rows per pass: lanes 0..31 and 32..63); every
+    // load is issued before the first store, from indices clamped to the list
+    {
+      constexpr int kPass = kMaxDrop / 2;
+      const int j = lane & 31, jc = ws.dl[min(j, k - 1)];
+      double gv[kPass];
+#pragma unroll
+      for (int q = 0; q < kPass; ++q) {
+        const int i = min(2 * q + (lane >> 5), k - 1);
+        gv[q] = G[ws.dl[i] * kMaxCand + jc];
+      }
+#pragma unroll
+      for (int q = 0; q < kPass; ++q) {
+        const int i = 2 * q + (lane >> 5);
+        if (i < k && j <= i) ws.a[i][j] = gv[q];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // Cholesky, lanes over rows (row i = lane & 31 in both halves; the half
+    // picks every other column of the update)
+    bool bad = false;
+    {
+      const int i = lane & 31, h = lane >> 5;
+      for (int p = 0; p < k; ++p) {
+        const double d = ws.a[p][p];
+        if (!(d > 0.0)) {
+          bad = true;
+          break;
+        }
+        const double is = 1.0 / sqrt(d);
+        __builtin_amdgcn_wave_barrier();
+        if (h == 0 && i > p && i < k) ws.a[i][p] *= is;
+        if (lane == 0) ws.a[p][p] = d * is;
+        __builtin_amdgcn_wave_barrier();
+        if (i > p && i < k) {
+          const double lip = ws.a[i][p];
+          for (int j = p + 1 + h; j <= i; j += 2) ws.a[i][j] -= lip * ws.a[j][p];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    const long long pix = (long long)(sys % (unsigned)g.plane);
+    const int gap = (int)(sys / (unsigned)g.plane);
+    const long long base = (long long)gap * g.plane + pix;   // the column in the lower slice
+    if (bad) {
+      if (lane == 0) atomicAdd(&ctr->bad_pivot, 1ull);
+      for (int t = 1 + lane; t <= nt; t += 64) {
+        const long long o = ((long long)gap * g.f + t) * g.plane + pix;
+        volume[o] = __builtin_nanf("");
+        if (variance) variance[o] = __builtin_nanf("");
+      }
+      if (lane == 0 && flags) flags[sys] = kFlagBadPivot;
+      continue;
+    }
+    // data values of the kept candidates (a kept candidate lies in the image)
+    const double z0 = keep0 ? (double)slices[base + off0] : 0.0;
+    const double z1 = keep1 ? (double)slices[base + off1] : 0.0;
+    for (int t0 = 1; t0 <= nt; t0 += 3) {
+      // right-hand sides: r = 0 the ones, r = 1..3 targets t0..t0+2 (the last repeated)
+      int tr[4];
+      tr[0] = 0;
+#pragma unroll
+      for (int r = 1; r < 4; ++r) tr[r] = min(t0 + r - 1, nt);
+      // y_r in lane-row form (row i = lane < k): u_r at the dropped candidates
+      double yv[4];
+      const int di = lane < k ? ws.dl[lane] : 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yv[r] = lane < k ? U[tr[r] * kMaxCand + di] : 0.0;
+      // forward: L y' = u_D
+      for (int p = 0; p < k; ++p) {
+        const double ipp = 1.0 / ws.a[p][p];
+        const double lip = (lane > p && lane < k) ? ws.a[lane][p] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double yp = lane_d(yv[r], p) * ipp;
+          yv[r] = lane == p ? yp : yv[r] - lip * yp;
+        }
+      }
+      // backward: L^T y = y'
+      for (int p = k - 1; p >= 0; --p) {
+        const double ipp = 1.0 / ws.a[p][p];
+        const double lpi = lane < p ? ws.a[p][lane] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double yp = lane_d(yv[r], p) * ipp;
+          yv[r] = lane == p ? yp : yv[r] - lpi * yp;
+        }
+      }
+      // x_r at the lane's candidates: u_r - sum_j G[d_j][c] y_r[j] (G symmetric)
+      double x0[4], x1[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        x0[r] = in0 ? U[tr[r] * kMaxCand + lane] : 0.0;
+        x1[r] = in1 ? U[tr[r] * kMaxCand + lane + 64] : 0.0;
+      }
+      // eight rows of G in flight at a time; rows past k reread row d_{k-1}
+      // and take y = 0 (lanes >= k hold zeros)
+      const int c0i = in0 ? lane : 0, c1i = in1 ? lane + 64 : 0;
+      for (int jb = 0; jb < k; jb += 8) {
+        double g0[8], g1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double* grow = G + ws.dl[min(jb + u, k - 1)] * kMaxCand;
+          g0[u] = grow[c0i];
+          g1[u] = grow[c1i];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double yj = lane_d(yv[r], jb + u);
+            x0[r] -= g0[u] * yj;
+            x1[r] -= g1[u] * yj;
+          }
+        }
+      }
+      // kept candidates only from here on
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        x0[r] = keep0 ? x0[r] : 0.0;
+        x1[r] = keep1 ? x1[r] : 0.0;
+      }
+      const double s1 = wave_sum(x0[0] + x1[0]);
+#pragma unroll
+      for (int r = 1; r < 4; ++r) {
+        const int t = t0 + r - 1;
+        if (t > nt) break;
+        const double st = wave_sum(x0[r] + x1[r]);
+        const double mu = (st - 1.0) / s1;
+        const double w0 = x0[r] - mu * x0[0], w1 = x1[r] - mu * x1[0];
+        const double c00 = in0 ? C0[(t - 1) * kMaxCand + lane] : 0.0;
+        const double c01 = in1 ? C0[(t - 1) * kMaxCand + lane + 64] : 0.0;
+        const double est = wave_sum(w0 * z0 + w1 * z1);
+        const double wc = wave_sum(w0 * c00 + w1 * c01);
+        if (lane == 0) {
+          const long long o = ((long long)gap * g.f + t) * g.plane + pix;
+          volume[o] = (float)est;
+          if (variance) variance[o] = (float)(sill - wc - mu);
+        }
+      }
+    }
+    if (lane == 0 && flags) flags[sys] = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
@@ -479,18 +728,31 @@ hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
 
 namespace okr {
 
-hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
-                          const Geometry& g, const Vario& v, double* W, double* wvar,
-                          float* volume, float* variance, uint8_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(1024), 0, s, v, g, W, wvar, c);
+int pattern_downdate_floor(const Geometry& g) {
+  if (g.drift) return g.ncand;
+  const int nb = g.f + 1 + g.drift;
+  for (int NB = 1; NB <= kMaxBlocks; ++NB) {
+    const int lo = std::max(1, 16 * (NB - 1) - nb + 1);
+    if (lo <= g.ncand - 1 && lo >= g.ncand - kMaxDrop) return lo;
+  }
+  return g.ncand;
+}
+
+hipError_t launch_pattern(const float* slices, const uint64_t* bits, const uint8_t* count,
+                          const uint32_t* perm, DevCounters* c, const Geometry& g,
+                          const Vario& v, double* pat, int nlo, float* volume,
+                          float* variance, uint8_t* flags, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(1024), 0, s, v, g, pat, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g.nslices < 2) return hipSuccess;
-  dim3 grid((g.nx + kPTX - 1) / kPTX, (g.ny + kPTY - 1) / kPTY, g.nslices - 1);
+  const double* W = pat + kPatW;
+  const double* wvar = pat + kPatVar;
+  dim3 tiles((g.nx + kPTX - 1) / kPTX, (g.ny + kPTY - 1) / kPTY, g.nslices - 1);
   switch (g.r) {
 #define OKR_PATTERN_R(RR)                                                                      \
   case RR:                                                                                     \
-    hipLaunchKernelGGL(pattern_apply_kernel<RR>, grid, dim3(256), 0, s, slices, count, g, W,   \
+    hipLaunchKernelGGL(pattern_apply_kernel<RR>, tiles, dim3(256), 0, s, slices, count, g, W,  \
                        wvar, volume, variance, flags);                                         \
     break;
     OKR_PATTERN_R(0)
@@ -501,6 +763,11 @@ hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters
     default:
       return hipErrorInvalidValue;
   }
+  e = hipGetLastError();
+  if (e != hipSuccess || nlo >= g.ncand) return e;
+  if (nlo < 1 || g.ncand - nlo > kMaxDrop || g.drift) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pattern_downdate_kernel, dim3(std::max(grid, 1)), dim3(64 * kDdWaves), 0, s,
+                     slices, bits, count, perm, c, g, v.sill, pat, nlo, volume, variance, flags);
   return hipGetLastError();
 }
 

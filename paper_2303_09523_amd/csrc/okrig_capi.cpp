@@ -37,7 +37,7 @@ struct okr_plan {
   uint8_t* count = nullptr;
   uint32_t* perm = nullptr;
   uint32_t* fallback = nullptr;
-  double* pattern_w = nullptr;  // full-window weights [f-1][kMaxCand] and variances [f-1]
+  double* pattern_w = nullptr;  // full-window weight cache (layout at kPatDoubles)
   okr::DevCounters* ctr = nullptr;
   double* tabs = nullptr;       // FP64 tables and derivatives
   float* tabs_f = nullptr;      // FP32 copies
@@ -433,7 +433,7 @@ okr_status okr_plan_create(const okr_problem* problem, void* hip_stream, okr_pla
     return st;
   }
   if (problem->algo != OKR_ALGO_PLAIN_PER_VOXEL) {
-    if ((st = dev_alloc(p, &p->pattern_w, (okr::kMaxUpsample - 1) * okr::kMaxCand + okr::kMaxUpsample)) !=
+    if ((st = dev_alloc(p, &p->pattern_w, okr::kPatDoubles)) !=
         OKR_OK) {
       free_plan(p);
       return st;
@@ -634,10 +634,11 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   if (p->prob.algo == OKR_ALGO_PATTERN_CACHE) {
     // the full-window systems from the cached FP64 weights; the rest below
     PhaseTimer t(p, OKR_PHASE_PATTERN);
-    OKR_HIP(p, okr::launch_pattern(d_slices, p->count, p->ctr, g, vario_of(vario), p->pattern_w,
-                                   p->pattern_w + (okr::kMaxUpsample - 1) * okr::kMaxCand,
-                                   d_volume, d_variance, d_flags, strm));
-    a.nmax = g.ncand - 1;
+    const int nlo = okr::pattern_downdate_floor(g);
+    OKR_HIP(p, okr::launch_pattern(d_slices, p->bits, p->count, p->perm, p->ctr, g,
+                                   vario_of(vario), p->pattern_w, nlo, d_volume, d_variance,
+                                   d_flags, p->num_cu * 4, strm));
+    a.nmax = nlo - 1;
   }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;
   // Precision control against refine_tol (per-voxel relative error), with the
@@ -1215,7 +1216,7 @@ constexpr size_t kOffTabs = kOffCtr + align256(sizeof(okr::DevCounters));
 constexpr size_t kOffTabsF = kOffTabs + align256(sizeof(double) * (4 * okr::kTcSize + 4 * okr::kT0Size));
 constexpr size_t kOffPattern = kOffTabsF + align256(sizeof(float) * (okr::kTcSize + okr::kT0Size));
 constexpr size_t kOffBits =
-    kOffPattern + align256(sizeof(double) * ((okr::kMaxUpsample - 1) * okr::kMaxCand + okr::kMaxUpsample));
+    kOffPattern + align256(sizeof(double) * okr::kPatDoubles);
 constexpr size_t kOffCount = kOffBits + align256(sizeof(uint64_t) * 2 * kStaticMaxSystems);
 constexpr size_t kOffPerm = kOffCount + align256(kStaticMaxSystems);
 constexpr size_t kOffFallback = kOffPerm + align256(sizeof(uint32_t) * kStaticMaxSystems);

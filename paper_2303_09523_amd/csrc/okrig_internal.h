@@ -16,6 +16,22 @@ constexpr int kT0Stride = 32;                      // target table: ((t-1)*2 + s
 constexpr int kT0Size = kMaxUpsample * kT0Stride;  // up to 14 targets used
 constexpr int kHist = 128;                         // histogram bins over n
 
+// Full-window weight cache (kernels_points.hip), one buffer of doubles:
+//   W   [f-1][kMaxCand]        weights of the full window per target
+//   var [kMaxUpsample]         their kriging variances
+//   G   [kMaxCand][kMaxCand]   C^{-1} of the full window (row-major)
+//   U   [kMaxUpsample][kMaxCand]  row 0: C^{-1} 1, row t: C^{-1} c0_t
+//   C0  [kMaxUpsample-1][kMaxCand] row t-1: c0_t of the full window
+// Systems that drop at most kMaxDrop candidates of the full window take
+// their weights from G and U (a k x k solve per system).
+constexpr int kMaxDrop = 32;
+constexpr int kPatW = 0;
+constexpr int kPatVar = kPatW + (kMaxUpsample - 1) * kMaxCand;
+constexpr int kPatG = kPatVar + kMaxUpsample;
+constexpr int kPatU = kPatG + kMaxCand * kMaxCand;
+constexpr int kPatC0 = kPatU + kMaxUpsample * kMaxCand;
+constexpr int kPatDoubles = kPatC0 + (kMaxUpsample - 1) * kMaxCand;
+
 // Per-system count byte: low 7 bits = n, bit 7 = floor-filled.
 constexpr uint8_t kFloorBit = 0x80;
 
@@ -122,9 +138,14 @@ int solve_blocks_needed(const Geometry& g);
 hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
 
 // ---- launchers (kernels_points.hip) ----
-hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
-                          const Geometry& g, const Vario& v, double* W, double* wvar,
-                          float* volume, float* variance, uint8_t* flags, hipStream_t s);
+// Smallest neighbour count whose systems the weight cache serves by the
+// k x k solve (whole size classes of the solve kernels, at most kMaxDrop
+// dropped candidates); ncand when none (or with the slice predictor).
+int pattern_downdate_floor(const Geometry& g);
+hipError_t launch_pattern(const float* slices, const uint64_t* bits, const uint8_t* count,
+                          const uint32_t* perm, DevCounters* c, const Geometry& g,
+                          const Vario& v, double* pat, int nlo, float* volume,
+                          float* variance, uint8_t* flags, int grid, hipStream_t s);
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
                          const int64_t* offset, const float* xyz, const float* val,
                          const float* txyz, float* est, float* var, float* weights,
