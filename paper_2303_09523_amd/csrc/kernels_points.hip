@@ -36,6 +36,19 @@ __device__ __forceinline__ double wave_sum(double x) {
   return lane_d(x, 0);
 }
 
+// K wave sums at once (the butterflies interleaved), lane 0's results made
+// uniform.
+template <int K>
+__device__ __forceinline__ void wave_sums_k(double (&x)[K]) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[q] += __shfl_xor(x[q], o, 64);
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] = lane_d(x[q], 0);
+}
+
+
 // C = L L^T in place in the lower triangle of A (row stride kPtLd), lanes over
 // rows. Returns true (uniformly) on a non-positive pivot.
 __device__ bool chol_lds(double* A, int n) {
@@ -517,8 +530,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 // of three (x_0 solved again for each group).
 struct DowndateScratch {
   double a[kMaxDrop][kMaxDrop + 1];   // G_DD, then its Cholesky factor (lower triangle)
+  double ip[kMaxDrop];                // 1 / L[p][p]
   int dl[kMaxDrop];                   // the dropped candidates, ascending
 };
+
+// 1/sqrt(x) in FP64: the hardware estimate (relative error about 5e-8) and
+// one second-order Newton step in residual form, y = y0 + y0 e (1/2 + 3e/8)
+// with e = 1 - x y0^2.
+__device__ __forceinline__ double rsq64(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y0, y0, 1.0);
+  return fma(y0 * e, fma(0.375, e, 0.5), y0);
+}
 constexpr int kDdWaves = 4;
 
 __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4))) void pattern_downdate_kernel(
@@ -555,7 +578,8 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
   for (unsigned long long it = start + (unsigned long long)blockIdx.x * kDdWaves + wid; it < end;
        it += (unsigned long long)gridDim.x * kDdWaves) {
     const unsigned sys = __builtin_amdgcn_readfirstlane(perm[it]);
-    const int k = nc - (count[sys] & 0x7f);
+    // uniform values made scalar, so that the loops over them stay scalar
+    const int k = __builtin_amdgcn_readfirstlane(nc - (count[sys] & 0x7f));
     if (k < 1 || k > kMaxDrop) continue;   // not a system of this range
     const uint64_t lo = bits[2ull * sys], hi = bits[2ull * sys + 1];
     const bool keep0 = in0 && ((lo >> lane) & 1ull);
@@ -583,26 +607,44 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // Cholesky, lanes over rows (row i = lane & 31 in both halves; the half
-    // picks every other column of the update)
+    // Cholesky, right-looking. Step p reads the pivot and column p, then
+    // updates the trailing triangle (lane: column j = p + 1 + (lane & 31),
+    // rows i = p + 1 + 2q + (lane >> 5)) in chunks of eight rows, each chunk's
+    // reads before its writes, to a_ij - l_ip l_jp, and writes the scaled
+    // column last (no read of the step needs it).
     bool bad = false;
     {
-      const int i = lane & 31, h = lane >> 5;
+      constexpr int kChunk = 4;   // row pairs per chunk
+      const int ho = lane >> 5;
       for (int p = 0; p < k; ++p) {
-        const double d = ws.a[p][p];
+        const double d = lane_d(ws.a[p][p], 0);
         if (!(d > 0.0)) {
           bad = true;
           break;
         }
-        const double is = 1.0 / sqrt(d);
-        __builtin_amdgcn_wave_barrier();
-        if (h == 0 && i > p && i < k) ws.a[i][p] *= is;
-        if (lane == 0) ws.a[p][p] = d * is;
-        __builtin_amdgcn_wave_barrier();
-        if (i > p && i < k) {
-          const double lip = ws.a[i][p];
-          for (int j = p + 1 + h; j <= i; j += 2) ws.a[i][j] -= lip * ws.a[j][p];
+        const double is = rsq64(d);
+        const int j = p + 1 + (lane & 31), jc = min(j, k - 1);
+        const double ljp = ws.a[jc][p] * is;
+        const int m = k - p - 1;   // trailing rows
+        for (int q0 = 0; 2 * q0 < m; q0 += kChunk) {
+          double lip[kChunk], aij[kChunk];
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) {
+            const int ic = min(p + 1 + 2 * (q0 + q) + ho, k - 1);
+            lip[q] = ws.a[ic][p] * is;
+            aij[q] = ws.a[ic][jc];
+          }
+#pragma unroll
+          for (int q = 0; q < kChunk; ++q) {
+            const int i = p + 1 + 2 * (q0 + q) + ho;
+            if (i < k && j <= i) ws.a[i][j] = aij[q] - lip[q] * ljp;
+          }
         }
+        if (lane == 0) {
+          ws.a[p][p] = d * is;
+          ws.ip[p] = is;
+        }
+        if (ho == 0 && j < k) ws.a[j][p] = ljp;
         __builtin_amdgcn_wave_barrier();
       }
     }
@@ -633,24 +675,47 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
       const int di = lane < k ? ws.dl[lane] : 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) yv[r] = lane < k ? U[tr[r] * kMaxCand + di] : 0.0;
-      // forward: L y' = u_D
-      for (int p = 0; p < k; ++p) {
-        const double ipp = 1.0 / ws.a[p][p];
-        const double lip = (lane > p && lane < k) ? ws.a[lane][p] : 0.0;
+      // forward: L y' = u_D; four steps' pivots and factor entries read
+      // ahead of their chains (indices clamped to the factor)
+      for (int p0 = 0; p0 < k; p0 += 4) {
+        double ipp[4], lip[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double yp = lane_d(yv[r], p) * ipp;
-          yv[r] = lane == p ? yp : yv[r] - lip * yp;
+        for (int u = 0; u < 4; ++u) {
+          const int pc = min(p0 + u, k - 1);
+          ipp[u] = ws.ip[pc];
+          lip[u] = ws.a[min(lane, k - 1)][pc];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = p0 + u;
+          if (p >= k) break;
+          const double l = (lane > p && lane < k) ? lip[u] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double yp = lane_d(yv[r], p) * ipp[u];
+            yv[r] = lane == p ? yp : yv[r] - l * yp;
+          }
         }
       }
       // backward: L^T y = y'
-      for (int p = k - 1; p >= 0; --p) {
-        const double ipp = 1.0 / ws.a[p][p];
-        const double lpi = lane < p ? ws.a[p][lane] : 0.0;
+      for (int p0 = k - 1; p0 >= 0; p0 -= 4) {
+        double ipp[4], lpi[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double yp = lane_d(yv[r], p) * ipp;
-          yv[r] = lane == p ? yp : yv[r] - lpi * yp;
+        for (int u = 0; u < 4; ++u) {
+          const int pc = max(p0 - u, 0);
+          ipp[u] = ws.ip[pc];
+          lpi[u] = ws.a[pc][min(lane, kMaxDrop - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = p0 - u;
+          if (p < 0) break;
+          const double l = lane < p ? lpi[u] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double yp = lane_d(yv[r], p) * ipp[u];
+            yv[r] = lane == p ? yp : yv[r] - l * yp;
+          }
         }
       }
       // x_r at the lane's candidates: u_r - sum_j G[d_j][c] y_r[j] (G symmetric)
@@ -687,22 +752,30 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
         x0[r] = keep0 ? x0[r] : 0.0;
         x1[r] = keep1 ? x1[r] : 0.0;
       }
-      const double s1 = wave_sum(x0[0] + x1[0]);
+      // 1'x_0 and 1'x_t, then w_t'z and w_t'c0_t, each set reduced together
+      double r1[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) r1[r] = x0[r] + x1[r];
+      wave_sums_k<4>(r1);
+      double r2[6], mu[3];
 #pragma unroll
       for (int r = 1; r < 4; ++r) {
-        const int t = t0 + r - 1;
-        if (t > nt) break;
-        const double st = wave_sum(x0[r] + x1[r]);
-        const double mu = (st - 1.0) / s1;
-        const double w0 = x0[r] - mu * x0[0], w1 = x1[r] - mu * x1[0];
-        const double c00 = in0 ? C0[(t - 1) * kMaxCand + lane] : 0.0;
-        const double c01 = in1 ? C0[(t - 1) * kMaxCand + lane + 64] : 0.0;
-        const double est = wave_sum(w0 * z0 + w1 * z1);
-        const double wc = wave_sum(w0 * c00 + w1 * c01);
-        if (lane == 0) {
+        mu[r - 1] = (r1[r] - 1.0) / r1[0];
+        const double w0 = x0[r] - mu[r - 1] * x0[0], w1 = x1[r] - mu[r - 1] * x1[0];
+        const double c00 = in0 ? C0[(tr[r] - 1) * kMaxCand + lane] : 0.0;
+        const double c01 = in1 ? C0[(tr[r] - 1) * kMaxCand + lane + 64] : 0.0;
+        r2[r - 1] = w0 * z0 + w1 * z1;
+        r2[r + 2] = w0 * c00 + w1 * c01;
+      }
+      wave_sums_k<6>(r2);
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          const int t = t0 + r - 1;
+          if (t > nt) break;
           const long long o = ((long long)gap * g.f + t) * g.plane + pix;
-          volume[o] = (float)est;
-          if (variance) variance[o] = (float)(sill - wc - mu);
+          volume[o] = (float)r2[r - 1];
+          if (variance) variance[o] = (float)(sill - r2[r + 2] - mu[r - 1]);
         }
       }
     }
