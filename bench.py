@@ -274,6 +274,17 @@ def edge_postpass_record(w, vol, args, reps: int = 5):
     return rec
 
 
+def downdate_floor(ncand, nb, max_drop=32):
+    """Smallest neighbour count the weight cache serves from the full
+    window's inverse (whole 16-wide size classes 16 (NB - 1) - nb < n <=
+    16 NB - nb that drop at most max_drop candidates); ncand when none."""
+    for NB in range(1, 9):
+        lo = max(1, 16 * (NB - 1) - nb + 1)
+        if ncand - max_drop <= lo <= ncand - 1:
+            return lo
+    return ncand
+
+
 def mcubes_record(w, s, vol, args, reps: int = 5):
     """Marching cubes of the reconstructed volume at the median of the known
     slices: library HIP-event time per call and the HBM roofline."""
@@ -502,9 +513,12 @@ def main():
             pc.execute(st, w.vario, et, volume=vol, variance=var)
         sc = pc.stats()
         pc.close()
+        ncand = 2 * (2 * w.radius + 1) ** 2
+        nlo = downdate_floor(ncand, w.upsample + 1)
         rec = {"workload": w.name, "pattern_cache": {
             "steps": args.steps,
-            "full_window_systems": int(sc["bucket"][2 * (2 * w.radius + 1) ** 2]),
+            "full_window_systems": int(sc["bucket"][ncand]),
+            "inverse_systems": int(sum(sc["bucket"][nlo:ncand])),
             "phase_ms_per_step": {k: round(v / args.steps, 3)
                                   for k, v in sc["phase_ms"].items() if v > 0}}}
         if args.calib_copy > 0:
@@ -685,10 +699,14 @@ def main():
         others["pattern_cache"] = {
             "value": kriged / (mc * 1e-3), "unit": "voxels/s", "ms_per_step": round(mc, 3),
             "dtype": DTYPES[args.precision] + " + f64 cached weights",
-            "full_window_systems": nfull, "accuracy": acc_c,
+            "full_window_systems": nfull,
+            "inverse_systems": int(sum(sc["bucket"][downdate_floor(ncand, w.upsample + 1):ncand])),
+            "accuracy": acc_c,
             "phase_ms": {"pattern": round(pat_ms, 3), "solve": round(sc["phase_ms"]["solve"], 3)},
-            # the pattern phase: the weights solve and the stencil apply; the
-            # apply's FP64 FMAs bound it (its HBM bytes take a tenth of the time)
+            # the pattern phase: the full window's weights, inverse and solves
+            # and the stencil apply; the apply's FP64 FMAs bound it (its HBM
+            # bytes take a tenth of the time). The systems from the window's
+            # inverse are timed with the solve phase.
             "roofline_pattern_apply": {
                 "bound": "alu", "achieved": round(pflop / (pat_ms * 1e-3) / 1e12, 2),
                 "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",

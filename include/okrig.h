@@ -176,8 +176,9 @@ typedef struct {
                                  last okr_stats_get: 0 placement, 1 tables, 2 selection,
                                  3 bucketing, 4 batched solve, 5 FP64 re-solve,
                                  6 plain per-voxel kernel, 7 leave-one-slice-out,
-                                 8 full-window pattern weights + application
-                                 (and the systems served from the window's inverse),
+                                 8 full-window pattern weights + application (the
+                                 systems served from the window's inverse count
+                                 under 4),
                                  9 marching cubes, edge post-pass: 10 shearlet
                                  coefficients, 11 edge thinning, 12 chain tracing and
                                  re-routing (with the copy of the input to the output) */

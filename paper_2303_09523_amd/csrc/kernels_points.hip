@@ -811,10 +811,9 @@ int pattern_downdate_floor(const Geometry& g) {
   return g.ncand;
 }
 
-hipError_t launch_pattern(const float* slices, const uint64_t* bits, const uint8_t* count,
-                          const uint32_t* perm, DevCounters* c, const Geometry& g,
-                          const Vario& v, double* pat, int nlo, float* volume,
-                          float* variance, uint8_t* flags, int grid, hipStream_t s) {
+hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
+                          const Geometry& g, const Vario& v, double* pat, float* volume,
+                          float* variance, uint8_t* flags, hipStream_t s) {
   hipLaunchKernelGGL(pattern_weights_kernel, dim3(1), dim3(1024), 0, s, v, g, pat, c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -836,8 +835,15 @@ hipError_t launch_pattern(const float* slices, const uint64_t* bits, const uint8
     default:
       return hipErrorInvalidValue;
   }
-  e = hipGetLastError();
-  if (e != hipSuccess || nlo >= g.ncand) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_downdate(const float* slices, const uint64_t* bits,
+                                   const uint8_t* count, const uint32_t* perm, DevCounters* c,
+                                   const Geometry& g, const Vario& v, const double* pat, int nlo,
+                                   float* volume, float* variance, uint8_t* flags, int grid,
+                                   hipStream_t s) {
+  if (g.nslices < 2 || nlo >= g.ncand) return hipSuccess;
   if (nlo < 1 || g.ncand - nlo > kMaxDrop || g.drift) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pattern_downdate_kernel, dim3(std::max(grid, 1)), dim3(64 * kDdWaves), 0, s,
                      slices, bits, count, perm, c, g, v.sill, pat, nlo, volume, variance, flags);

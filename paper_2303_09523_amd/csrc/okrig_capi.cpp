@@ -634,10 +634,17 @@ okr_status enqueue_execute(okr_plan* p, hipStream_t strm, const okr_variogram* v
   if (p->prob.algo == OKR_ALGO_PATTERN_CACHE) {
     // the full-window systems from the cached FP64 weights; the rest below
     PhaseTimer t(p, OKR_PHASE_PATTERN);
+    OKR_HIP(p, okr::launch_pattern(d_slices, p->count, p->ctr, g, vario_of(vario), p->pattern_w,
+                                   d_volume, d_variance, d_flags, strm));
+  }
+  if (p->prob.algo == OKR_ALGO_PATTERN_CACHE) {
+    // the systems that drop at most kMaxDrop window candidates, from the
+    // window's inverse (timed with the batched solve, whose systems they are)
+    PhaseTimer t(p, OKR_PHASE_SOLVE);
     const int nlo = okr::pattern_downdate_floor(g);
-    OKR_HIP(p, okr::launch_pattern(d_slices, p->bits, p->count, p->perm, p->ctr, g,
-                                   vario_of(vario), p->pattern_w, nlo, d_volume, d_variance,
-                                   d_flags, p->num_cu * 4, strm));
+    OKR_HIP(p, okr::launch_pattern_downdate(d_slices, p->bits, p->count, p->perm, p->ctr, g,
+                                            vario_of(vario), p->pattern_w, nlo, d_volume,
+                                            d_variance, d_flags, p->num_cu * 4, strm));
     a.nmax = nlo - 1;
   }
   const bool mixed = p->prob.precision == OKR_MIXED_FP16 || p->prob.precision == OKR_MIXED_BF16;

@@ -142,10 +142,17 @@ hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
 // k x k solve (whole size classes of the solve kernels, at most kMaxDrop
 // dropped candidates); ncand when none (or with the slice predictor).
 int pattern_downdate_floor(const Geometry& g);
-hipError_t launch_pattern(const float* slices, const uint64_t* bits, const uint8_t* count,
-                          const uint32_t* perm, DevCounters* c, const Geometry& g,
-                          const Vario& v, double* pat, int nlo, float* volume,
-                          float* variance, uint8_t* flags, int grid, hipStream_t s);
+// The full window's weights, inverse and solves, then its systems' estimates.
+hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,
+                          const Geometry& g, const Vario& v, double* pat, float* volume,
+                          float* variance, uint8_t* flags, hipStream_t s);
+// The systems with neighbour counts nlo .. ncand - 1 from the full window's
+// inverse (after launch_pattern and the bucketing).
+hipError_t launch_pattern_downdate(const float* slices, const uint64_t* bits,
+                                   const uint8_t* count, const uint32_t* perm, DevCounters* c,
+                                   const Geometry& g, const Vario& v, const double* pat, int nlo,
+                                   float* volume, float* variance, uint8_t* flags, int grid,
+                                   hipStream_t s);
 hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
                          const int64_t* offset, const float* xyz, const float* val,
                          const float* txyz, float* est, float* var, float* weights,
