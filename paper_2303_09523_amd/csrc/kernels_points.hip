@@ -36,16 +36,33 @@ __device__ __forceinline__ double wave_sum(double x) {
   return lane_d(x, 0);
 }
 
-// K wave sums at once (the butterflies interleaved), lane 0's results made
-// uniform.
+// K wave sums at once, on the DPP network: quad_perm [1,0,3,2] and [2,3,0,1],
+// row_ror:4 and row_ror:8 give every lane its 16-lane row's sum; row_bcast:15
+// (into rows 1 and 3) and row_bcast:31 (into rows 2 and 3) then leave the
+// wave's sum in lane 63, whose value is made uniform.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 template <int K>
 __device__ __forceinline__ void wave_sums_k(double (&x)[K]) {
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1)
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0xB1, 0xf>(x[q]);
 #pragma unroll
-    for (int q = 0; q < K; ++q) x[q] += __shfl_xor(x[q], o, 64);
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0x4E, 0xf>(x[q]);
 #pragma unroll
-  for (int q = 0; q < K; ++q) x[q] = lane_d(x[q], 0);
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0x124, 0xf>(x[q]);
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0x128, 0xf>(x[q]);
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0x142, 0xa>(x[q]);
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] += dpp64<0x143, 0xc>(x[q]);
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[q] = lane_d(x[q], 63);
 }
 
 
@@ -544,6 +561,26 @@ __device__ __forceinline__ double rsq64(double x) {
 }
 constexpr int kDdWaves = 4;
 
+// G_DD (lower triangle) into LDS, two rows per pass (lanes 0..31 and 32..63);
+// every load is issued before the first store, from indices clamped to the
+// list. PASSES * 2 >= k.
+template <int PASSES>
+__device__ __forceinline__ void gather_gdd(DowndateScratch& ws, const double* __restrict__ G,
+                                           int k, int lane) {
+  const int j = lane & 31, jc = ws.dl[min(j, k - 1)];
+  double gv[PASSES];
+#pragma unroll
+  for (int q = 0; q < PASSES; ++q) {
+    const int i = min(2 * q + (lane >> 5), k - 1);
+    gv[q] = G[ws.dl[i] * kMaxCand + jc];
+  }
+#pragma unroll
+  for (int q = 0; q < PASSES; ++q) {
+    const int i = 2 * q + (lane >> 5);
+    if (i < k && j <= i) ws.a[i][j] = gv[q];
+  }
+}
+
 __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4))) void pattern_downdate_kernel(
     const float* __restrict__ slices, const uint64_t* __restrict__ bits,
     const uint8_t* __restrict__ count, const uint32_t* __restrict__ perm,
@@ -589,62 +626,82 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
     if (in0 && !keep0) ws.dl[__popcll(m0 & below)] = lane;
     if (in1 && !keep1) ws.dl[__popcll(m0) + __popcll(m1 & below)] = lane + 64;
     __builtin_amdgcn_wave_barrier();
-    // G_DD, lower triangle (two rows per pass: lanes 0..31 and 32..63); every
-    // load is issued before the first store, from indices clamped to the list
-    {
-      constexpr int kPass = kMaxDrop / 2;
-      const int j = lane & 31, jc = ws.dl[min(j, k - 1)];
-      double gv[kPass];
-#pragma unroll
-      for (int q = 0; q < kPass; ++q) {
-        const int i = min(2 * q + (lane >> 5), k - 1);
-        gv[q] = G[ws.dl[i] * kMaxCand + jc];
-      }
-#pragma unroll
-      for (int q = 0; q < kPass; ++q) {
-        const int i = 2 * q + (lane >> 5);
-        if (i < k && j <= i) ws.a[i][j] = gv[q];
-      }
-    }
+    // G_DD, lower triangle
+    if (k <= 8)
+      gather_gdd<4>(ws, G, k, lane);
+    else if (k <= 16)
+      gather_gdd<8>(ws, G, k, lane);
+    else
+      gather_gdd<kMaxDrop / 2>(ws, G, k, lane);
     __builtin_amdgcn_wave_barrier();
-    // Cholesky, right-looking. Step p reads the pivot and column p, then
-    // updates the trailing triangle (lane: column j = p + 1 + (lane & 31),
-    // rows i = p + 1 + 2q + (lane >> 5)) in chunks of eight rows, each chunk's
-    // reads before its writes, to a_ij - l_ip l_jp, and writes the scaled
-    // column last (no read of the step needs it).
+    // Cholesky, right-looking, two columns per step. A step reads the 2 x 2
+    // pivot block and columns p, p + 1, then updates the trailing triangle
+    // (lane: column j = p + 2 + (lane & 31), rows i = p + 2 + 2q + (lane >> 5))
+    // in chunks of eight rows, each chunk's reads before its writes, to
+    // a_ij - l_i0 l_j0 - l_i1 l_j1 (the two rank-1 updates in turn), and writes
+    // the two scaled columns last (no read of the step needs them).
     bool bad = false;
     {
       constexpr int kChunk = 4;   // row pairs per chunk
       const int ho = lane >> 5;
-      for (int p = 0; p < k; ++p) {
-        const double d = lane_d(ws.a[p][p], 0);
-        if (!(d > 0.0)) {
+      int p = 0;
+      for (; p + 1 < k; p += 2) {
+        const double d0 = lane_d(ws.a[p][p], 0);
+        const double a10 = lane_d(ws.a[p + 1][p], 0);
+        const double a11 = lane_d(ws.a[p + 1][p + 1], 0);
+        if (!(d0 > 0.0)) {
           bad = true;
           break;
         }
-        const double is = rsq64(d);
-        const int j = p + 1 + (lane & 31), jc = min(j, k - 1);
-        const double ljp = ws.a[jc][p] * is;
-        const int m = k - p - 1;   // trailing rows
+        const double is0 = rsq64(d0);
+        const double l10 = a10 * is0;
+        const double d1 = a11 - l10 * l10;
+        if (!(d1 > 0.0)) {
+          bad = true;
+          break;
+        }
+        const double is1 = rsq64(d1);
+        const int j = p + 2 + (lane & 31), jc = min(j, k - 1);
+        const double lj0 = ws.a[jc][p] * is0;
+        const double lj1 = (ws.a[jc][p + 1] - lj0 * l10) * is1;
+        const int m = k - p - 2;   // trailing rows
         for (int q0 = 0; 2 * q0 < m; q0 += kChunk) {
-          double lip[kChunk], aij[kChunk];
+          double li0[kChunk], li1[kChunk], aij[kChunk];
 #pragma unroll
           for (int q = 0; q < kChunk; ++q) {
-            const int ic = min(p + 1 + 2 * (q0 + q) + ho, k - 1);
-            lip[q] = ws.a[ic][p] * is;
+            const int ic = min(p + 2 + 2 * (q0 + q) + ho, k - 1);
+            li0[q] = ws.a[ic][p] * is0;
+            li1[q] = (ws.a[ic][p + 1] - li0[q] * l10) * is1;
             aij[q] = ws.a[ic][jc];
           }
 #pragma unroll
           for (int q = 0; q < kChunk; ++q) {
-            const int i = p + 1 + 2 * (q0 + q) + ho;
-            if (i < k && j <= i) ws.a[i][j] = aij[q] - lip[q] * ljp;
+            const int i = p + 2 + 2 * (q0 + q) + ho;
+            if (i < k && j <= i) ws.a[i][j] = (aij[q] - li0[q] * lj0) - li1[q] * lj1;
           }
         }
         if (lane == 0) {
+          ws.a[p][p] = d0 * is0;
+          ws.a[p + 1][p] = l10;
+          ws.a[p + 1][p + 1] = d1 * is1;
+          ws.ip[p] = is0;
+          ws.ip[p + 1] = is1;
+        }
+        if (ho == 0 && j < k) {
+          ws.a[j][p] = lj0;
+          ws.a[j][p + 1] = lj1;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (!bad && p < k) {   // the last column of an odd k
+        const double d = lane_d(ws.a[p][p], 0);
+        if (!(d > 0.0)) {
+          bad = true;
+        } else if (lane == 0) {
+          const double is = rsq64(d);
           ws.a[p][p] = d * is;
           ws.ip[p] = is;
         }
-        if (ho == 0 && j < k) ws.a[j][p] = ljp;
         __builtin_amdgcn_wave_barrier();
       }
     }
