@@ -161,6 +161,37 @@ __device__ void subst_lds(const double* A, int n, double (&b)[2], double (&c)[2]
   }
 }
 
+// subst_lds for NR right-hand sides at once (the independent chains of one
+// step interleave), with the reciprocal of each pivot taken once.
+template <int NR>
+__device__ void subst_lds_n(const double* A, int n, double (&b)[NR][2]) {
+  const int lane = threadIdx.x & 63;
+  for (int k = 0; k < n; ++k) {
+    const double ikk = 1.0 / A[k * kPtLd + k];
+    const int hk = k >> 6, lk = k & 63;
+    const double l0 = (lane > k && lane < n) ? A[lane * kPtLd + k] : 0.0;
+    const double l1 = (lane + 64 > k && lane + 64 < n) ? A[(lane + 64) * kPtLd + k] : 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double y = (hk ? lane_d(b[r][1], lk) : lane_d(b[r][0], lk)) * ikk;
+      b[r][0] = lane == k ? y : b[r][0] - l0 * y;
+      b[r][1] = lane + 64 == k ? y : b[r][1] - l1 * y;
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const double ikk = 1.0 / A[k * kPtLd + k];
+    const int hk = k >> 6, lk = k & 63;
+    const double l0 = lane < k ? A[k * kPtLd + lane] : 0.0;
+    const double l1 = lane + 64 < k ? A[k * kPtLd + lane + 64] : 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double x = (hk ? lane_d(b[r][1], lk) : lane_d(b[r][0], lk)) * ikk;
+      b[r][0] = lane == k ? x : b[r][0] - l0 * x;
+      b[r][1] = lane + 64 == k ? x : b[r][1] - l1 * x;
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void points_kernel(Vario v, long long nsys,
                                                     const int32_t* __restrict__ count,
                                                     const int64_t* __restrict__ offset,
@@ -306,25 +337,26 @@ __global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry
     for (int i = threadIdx.x; i < kMaxUpsample * kMaxCand; i += blockDim.x) U[i] = __builtin_nan("");
     return;
   }
-  // G = C^{-1}, two columns per solve (rows by symmetry: row c of G is C^{-1} e_c)
-  for (int c = 2 * wid; c < n; c += 2 * (int)(blockDim.x >> 6)) {
-    double e0[2], e1[2];
+  // G = C^{-1}, seven columns per wave (rows by symmetry: row c of G is
+  // C^{-1} e_c); sixteen waves cover the 98 columns in one pass
+  {
+    constexpr int NR = 7;
+    for (int c0 = NR * wid; c0 < n; c0 += NR * (int)(blockDim.x >> 6)) {
+      double e[NR][2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = lane + 64 * h;
-      e0[h] = i == c ? 1.0 : 0.0;
-      e1[h] = i == c + 1 ? 1.0 : 0.0;
-    }
-    subst_lds(A, n, e0, e1);
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = lane + 64 * h;
-      if (i < n) {
-        G[c * kMaxCand + i] = e0[h];
-        if (c + 1 < n) G[(c + 1) * kMaxCand + i] = e1[h];
-      }
+        for (int h = 0; h < 2; ++h) e[r][h] = lane + 64 * h == c0 + r ? 1.0 : 0.0;
+      subst_lds_n<NR>(A, n, e);
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = lane + 64 * h;
+          if (c0 + r < n && i < n) G[(c0 + r) * kMaxCand + i] = e[r][h];
+        }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
   // each wave solves the targets t = 1 + wid (mod waves) against the shared factor
   // slice of each candidate (0 lower, 1 upper) and, with the drift, X_s = C^-1 s
