@@ -580,6 +580,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 struct DowndateScratch {
   double a[kMaxDrop][kMaxDrop + 1];   // G_DD, then its Cholesky factor (lower triangle)
   double ip[kMaxDrop];                // 1 / L[p][p]
+  double y[kMaxDrop][4];              // the solutions y_r by row
   int dl[kMaxDrop];                   // the dropped candidates, ascending
 };
 
@@ -814,8 +815,15 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
         x0[r] = in0 ? U[tr[r] * kMaxCand + lane] : 0.0;
         x1[r] = in1 ? U[tr[r] * kMaxCand + lane + 64] : 0.0;
       }
+      // the solutions to LDS, read back as broadcasts
+      if (lane < kMaxDrop) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ws.y[lane][r] = yv[r];
+      }
+      __builtin_amdgcn_wave_barrier();
       // eight rows of G in flight at a time; rows past k reread row d_{k-1}
-      // and take y = 0 (lanes >= k hold zeros)
+      // and take y = 0 (rows k..31 of y hold the zeros of lanes >= k, and a
+      // row index past 31 occurs only for k < 32, where row 31 is such a row)
       const int c0i = in0 ? lane : 0, c1i = in1 ? lane + 64 : 0;
       for (int jb = 0; jb < k; jb += 8) {
         double g0[8], g1[8];
@@ -829,12 +837,13 @@ __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4
         for (int u = 0; u < 8; ++u) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const double yj = lane_d(yv[r], jb + u);
+            const double yj = ws.y[min(jb + u, kMaxDrop - 1)][r];
             x0[r] -= g0[u] * yj;
             x1[r] -= g1[u] * yj;
           }
         }
       }
+      __builtin_amdgcn_wave_barrier();
       // kept candidates only from here on
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
