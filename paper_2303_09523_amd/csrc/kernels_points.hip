@@ -444,13 +444,11 @@ __global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry
 constexpr int kPTX = 64, kRows = 4, kPTY = 4 * kRows, kTGroup = 3;
 
 template <int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void pattern_apply_kernel(const float* __restrict__ slices,
-                                                            const uint8_t* __restrict__ count,
-                                                            Geometry g, const double* __restrict__ W,
-                                                            const double* __restrict__ wvar,
-                                                            float* __restrict__ volume,
-                                                            float* __restrict__ variance,
-                                                            uint8_t* __restrict__ flags) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void pattern_apply_kernel(const float* __restrict__ slices, const uint8_t* __restrict__ count,
+                          Geometry g, const double* __restrict__ W,
+                          const double* __restrict__ wvar, float* __restrict__ volume,
+                          float* __restrict__ variance, uint8_t* __restrict__ flags) {
   constexpr int Wn = 2 * R + 1, W2 = Wn * Wn;
   constexpr int kTX = kPTX + 2 * R, kTY = kPTY + 2 * R;
   __shared__ double tile[2][kTY][kTX];
@@ -572,8 +570,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void p
 //   x_r = C_KK^{-1} b_K = u_K - G_KD y_r,   G_DD y_r = u_D,
 // exactly (up to rounding) and whatever b holds at the dropped candidates.
 // Per system one wave: the k x k matrix G_DD is gathered into LDS and
-// factored (lanes over rows), the k-vectors y_r are solved with lanes over
-// rows, and x_r for the kept candidates (two per lane) follow from rows of G.
+// factored two columns per step (columns over lanes), the k-vectors y_r are
+// solved with lanes over rows, and x_r for the kept candidates (two per lane)
+// follow from rows of G.
 // Then mu_t = (1'x_t - 1) / 1'x_0, w_t = x_t - mu_t x_0, the estimate w_t'z
 // and the variance sill - w_t'c0_t - mu_t, all in FP64. Targets go in groups
 // of three (x_0 solved again for each group).
@@ -614,7 +613,8 @@ __device__ __forceinline__ void gather_gdd(DowndateScratch& ws, const double* __
   }
 }
 
-__global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4))) void pattern_downdate_kernel(
+__global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4)))
+void pattern_downdate_kernel(
     const float* __restrict__ slices, const uint64_t* __restrict__ bits,
     const uint8_t* __restrict__ count, const uint32_t* __restrict__ perm,
     DevCounters* __restrict__ ctr, Geometry g, double sill, const double* __restrict__ pat,
