@@ -9,7 +9,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libokrig.so")
+# OKRIG_LIB names another build of the same library (the host-sanitizer test
+# loads an instrumented one); there is no other library and no fallback.
+LIB_PATH = os.environ.get("OKRIG_LIB") or os.path.join(HERE, "libokrig.so")
 
 OKR_OK = 0
 STATUS_NAMES = {0: "OKR_OK", 1: "OKR_E_INVALID_ARG", 2: "OKR_E_SHAPE", 3: "OKR_E_NONFINITE",
