@@ -514,9 +514,9 @@ void pattern_apply_kernel(const float* __restrict__ slices, const uint8_t* __res
 #pragma unroll
       for (int yy = 0; yy < Wn; ++yy) {
         // The weights of this window row (3 x W doubles in SGPRs). An opaque
-        // row offset and a scheduling barrier keep each row's loads in its
-        // step: the 2 x W x W x 3 weights do not fit in SGPRs.
-        __builtin_amdgcn_sched_barrier(0);
+        // row offset keeps the rows' loads apart (not merged into wide loads
+        // of every row at the top): the 2 x W x W x 3 weights do not fit in
+        // SGPRs.
         int off = (sl * Wn + yy) * Wn;   // slot sl * W2 + yy * Wn
         asm volatile("" : "+s"(off));
         double wr[kTGroup][Wn];
