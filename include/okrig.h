@@ -86,9 +86,8 @@ typedef enum { OKR_FP32 = 0, OKR_MIXED_FP16 = 1, OKR_MIXED_BF16 = 2, OKR_FP64 = 
  * PATTERN_CACHE: BATCHED, except that the systems keeping the whole window
  * (the same matrix for all of them, by translation invariance) take weights
  * and variances computed once per launch in FP64 and applied as FP64 dot
- * products, and, without the slice predictor, the systems of the size
- * classes that drop at most 32 candidates of the window take theirs from the
- * window's FP64 inverse (the block-inverse identity, one k x k solve per
+ * products, and the systems of the size classes that drop at most 32
+ * candidates of the window take theirs from the window's FP64 inverse (the block-inverse identity, one k x k solve per
  * system for its k dropped candidates); the other systems are solved as in
  * BATCHED at the plan's precision. */
 typedef enum { OKR_ALGO_BATCHED = 0, OKR_ALGO_PLAIN_PER_VOXEL = 1,

@@ -373,6 +373,12 @@ __global__ __launch_bounds__(1024) void pattern_weights_kernel(Vario v, Geometry
     xs[0] = sl[0];
     xs[1] = sl[1];
     subst_lds(A, n, xs, unused);
+    // C^{-1} s in the last row of U (f <= kMaxUpsample - 1 with the predictor)
+    if (wid == 0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (lane + 64 * h < n) U[(kMaxUpsample - 1) * kMaxCand + lane + 64 * h] = xs[h];
+    }
   }
   for (int t = 1 + wid; t < g.f; t += blockDim.x >> 6) {
     double b1[2], bc[2];
@@ -579,7 +585,7 @@ void pattern_apply_kernel(const float* __restrict__ slices, const uint8_t* __res
 struct DowndateScratch {
   double a[kMaxDrop][kMaxDrop + 1];   // G_DD, then its Cholesky factor (lower triangle)
   double ip[kMaxDrop];                // 1 / L[p][p]
-  double y[kMaxDrop][4];              // the solutions y_r by row
+  double y[kMaxDrop][5];              // the solutions y_r by row
   int dl[kMaxDrop];                   // the dropped candidates, ascending
 };
 
@@ -613,6 +619,7 @@ __device__ __forceinline__ void gather_gdd(DowndateScratch& ws, const double* __
   }
 }
 
+template <bool DRIFT>
 __global__ __launch_bounds__(64 * kDdWaves) __attribute__((amdgpu_waves_per_eu(4)))
 void pattern_downdate_kernel(
     const float* __restrict__ slices, const uint64_t* __restrict__ bits,
@@ -634,15 +641,18 @@ void pattern_downdate_kernel(
   const bool in0 = lane < nc, in1 = lane + 64 < nc;
   long long off0 = 0, off1 = 0;
   int dy0 = 0, dx0 = 0, dy1 = 0, dx1 = 0;
+  double sl0 = 0.0, sl1 = 0.0;   // the candidates' slices (the second predictor)
   {
     int s;
     if (in0) {
       cand_xyz(lane, g, &dx0, &dy0, &s);
       off0 = (long long)s * g.plane + (long long)dy0 * g.nx + dx0;
+      sl0 = (double)s;
     }
     if (in1) {
       cand_xyz(lane + 64, g, &dx1, &dy1, &s);
       off1 = (long long)s * g.plane + (long long)dy1 * g.nx + dx1;
+      sl1 = (double)s;
     }
   }
   for (unsigned long long it = start + (unsigned long long)blockIdx.x * kDdWaves + wid; it < end;
@@ -754,17 +764,20 @@ void pattern_downdate_kernel(
     // data values of the kept candidates (a kept candidate lies in the image)
     const double z0 = keep0 ? (double)slices[base + off0] : 0.0;
     const double z1 = keep1 ? (double)slices[base + off1] : 0.0;
+    // right-hand sides of a group: r = 0 the ones, r = 1..3 targets t0..t0+2
+    // (the last repeated), and with the slice predictor r = 4 the slices
+    constexpr int NR = DRIFT ? 5 : 4;
     for (int t0 = 1; t0 <= nt; t0 += 3) {
-      // right-hand sides: r = 0 the ones, r = 1..3 targets t0..t0+2 (the last repeated)
-      int tr[4];
+      int tr[NR];
       tr[0] = 0;
 #pragma unroll
       for (int r = 1; r < 4; ++r) tr[r] = min(t0 + r - 1, nt);
+      if (DRIFT) tr[NR - 1] = kMaxUpsample - 1;
       // y_r in lane-row form (row i = lane < k): u_r at the dropped candidates
-      double yv[4];
+      double yv[NR];
       const int di = lane < k ? ws.dl[lane] : 0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) yv[r] = lane < k ? U[tr[r] * kMaxCand + di] : 0.0;
+      for (int r = 0; r < NR; ++r) yv[r] = lane < k ? U[tr[r] * kMaxCand + di] : 0.0;
       // forward: L y' = u_D; four steps' pivots and factor entries read
       // ahead of their chains (indices clamped to the factor)
       for (int p0 = 0; p0 < k; p0 += 4) {
@@ -781,7 +794,7 @@ void pattern_downdate_kernel(
           if (p >= k) break;
           const double l = (lane > p && lane < k) ? lip[u] : 0.0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+          for (int r = 0; r < NR; ++r) {
             const double yp = lane_d(yv[r], p) * ipp[u];
             yv[r] = lane == p ? yp : yv[r] - l * yp;
           }
@@ -802,23 +815,23 @@ void pattern_downdate_kernel(
           if (p < 0) break;
           const double l = lane < p ? lpi[u] : 0.0;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+          for (int r = 0; r < NR; ++r) {
             const double yp = lane_d(yv[r], p) * ipp[u];
             yv[r] = lane == p ? yp : yv[r] - l * yp;
           }
         }
       }
       // x_r at the lane's candidates: u_r - sum_j G[d_j][c] y_r[j] (G symmetric)
-      double x0[4], x1[4];
+      double x0[NR], x1[NR];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < NR; ++r) {
         x0[r] = in0 ? U[tr[r] * kMaxCand + lane] : 0.0;
         x1[r] = in1 ? U[tr[r] * kMaxCand + lane + 64] : 0.0;
       }
       // the solutions to LDS, read back as broadcasts
       if (lane < kMaxDrop) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) ws.y[lane][r] = yv[r];
+        for (int r = 0; r < NR; ++r) ws.y[lane][r] = yv[r];
       }
       __builtin_amdgcn_wave_barrier();
       // eight rows of G in flight at a time; rows past k reread row d_{k-1}
@@ -836,7 +849,7 @@ void pattern_downdate_kernel(
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
+          for (int r = 0; r < NR; ++r) {
             const double yj = ws.y[min(jb + u, kMaxDrop - 1)][r];
             x0[r] -= g0[u] * yj;
             x1[r] -= g1[u] * yj;
@@ -846,24 +859,58 @@ void pattern_downdate_kernel(
       __builtin_amdgcn_wave_barrier();
       // kept candidates only from here on
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < NR; ++r) {
         x0[r] = keep0 ? x0[r] : 0.0;
         x1[r] = keep1 ? x1[r] : 0.0;
       }
-      // 1'x_0 and 1'x_t, then w_t'z and w_t'c0_t, each set reduced together
-      double r1[4];
+      // the Lagrange multipliers of each target from sums over the kept
+      // candidates, then w_t'z and w_t'c0_t, each set of sums reduced together
+      double r2[6], lagr[3];
+      double wt0[3], wt1[3];
+      if (!DRIFT) {
+        // mu_t = (1'x_t - 1) / 1'x_0, w_t = x_t - mu_t x_0
+        double r1[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) r1[r] = x0[r] + x1[r];
-      wave_sums_k<4>(r1);
-      double r2[6], mu[3];
+        for (int r = 0; r < 4; ++r) r1[r] = x0[r] + x1[r];
+        wave_sums_k<4>(r1);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          lagr[r - 1] = (r1[r] - 1.0) / r1[0];
+          wt0[r - 1] = x0[r] - lagr[r - 1] * x0[0];
+          wt1[r - 1] = x1[r] - lagr[r - 1] * x1[0];
+        }
+      } else {
+        // with the slice s as second predictor (x_s = x[4]): the 2 x 2 system
+        // [[1'x_1, 1'x_s], [1'x_s, s'x_s]] (p1, ps) = (1'x_t - 1, s'x_t - t/f),
+        // w_t = x_t - p1 x_1 - ps x_s, multiplier term p1 + ps t/f
+        double r1[9];
+        r1[0] = x0[0] + x1[0];
+        r1[1] = x0[NR - 1] + x1[NR - 1];
+        r1[2] = sl0 * x0[NR - 1] + sl1 * x1[NR - 1];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          r1[2 + r] = x0[r] + x1[r];
+          r1[5 + r] = sl0 * x0[r] + sl1 * x1[r];
+        }
+        wave_sums_k<9>(r1);
+        const double g11 = r1[0], g12 = r1[1], g22 = r1[2];
+        const double det = g11 * g22 - g12 * g12;
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          const double qt = (double)tr[r] / g.f;
+          const double e1 = r1[2 + r] - 1.0, e2 = r1[5 + r] - qt;
+          const double p1 = (g22 * e1 - g12 * e2) / det, ps = (g11 * e2 - g12 * e1) / det;
+          lagr[r - 1] = p1 + ps * qt;
+          wt0[r - 1] = x0[r] - p1 * x0[0] - ps * x0[NR - 1];
+          wt1[r - 1] = x1[r] - p1 * x1[0] - ps * x1[NR - 1];
+        }
+      }
 #pragma unroll
       for (int r = 1; r < 4; ++r) {
-        mu[r - 1] = (r1[r] - 1.0) / r1[0];
-        const double w0 = x0[r] - mu[r - 1] * x0[0], w1 = x1[r] - mu[r - 1] * x1[0];
         const double c00 = in0 ? C0[(tr[r] - 1) * kMaxCand + lane] : 0.0;
         const double c01 = in1 ? C0[(tr[r] - 1) * kMaxCand + lane + 64] : 0.0;
-        r2[r - 1] = w0 * z0 + w1 * z1;
-        r2[r + 2] = w0 * c00 + w1 * c01;
+        r2[r - 1] = wt0[r - 1] * z0 + wt1[r - 1] * z1;
+        r2[r + 2] = wt0[r - 1] * c00 + wt1[r - 1] * c01;
       }
       wave_sums_k<6>(r2);
       if (lane == 0) {
@@ -873,7 +920,7 @@ void pattern_downdate_kernel(
           if (t > nt) break;
           const long long o = ((long long)gap * g.f + t) * g.plane + pix;
           volume[o] = (float)r2[r - 1];
-          if (variance) variance[o] = (float)(sill - r2[r + 2] - mu[r - 1]);
+          if (variance) variance[o] = (float)(sill - r2[r + 2] - lagr[r - 1]);
         }
       }
     }
@@ -900,7 +947,6 @@ hipError_t launch_points(const Vario& v, long long nsys, const int32_t* count,
 namespace okr {
 
 int pattern_downdate_floor(const Geometry& g) {
-  if (g.drift) return g.ncand;
   const int nb = g.f + 1 + g.drift;
   for (int NB = 1; NB <= kMaxBlocks; ++NB) {
     const int lo = std::max(1, 16 * (NB - 1) - nb + 1);
@@ -942,9 +988,16 @@ hipError_t launch_pattern_downdate(const float* slices, const uint64_t* bits,
                                    float* volume, float* variance, uint8_t* flags, int grid,
                                    hipStream_t s) {
   if (g.nslices < 2 || nlo >= g.ncand) return hipSuccess;
-  if (nlo < 1 || g.ncand - nlo > kMaxDrop || g.drift) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pattern_downdate_kernel, dim3(std::max(grid, 1)), dim3(64 * kDdWaves), 0, s,
-                     slices, bits, count, perm, c, g, v.sill, pat, nlo, volume, variance, flags);
+  if (nlo < 1 || g.ncand - nlo > kMaxDrop || g.f + g.drift > kMaxUpsample)
+    return hipErrorInvalidValue;
+  if (g.drift)
+    hipLaunchKernelGGL(pattern_downdate_kernel<true>, dim3(std::max(grid, 1)),
+                       dim3(64 * kDdWaves), 0, s, slices, bits, count, perm, c, g, v.sill, pat,
+                       nlo, volume, variance, flags);
+  else
+    hipLaunchKernelGGL(pattern_downdate_kernel<false>, dim3(std::max(grid, 1)),
+                       dim3(64 * kDdWaves), 0, s, slices, bits, count, perm, c, g, v.sill, pat,
+                       nlo, volume, variance, flags);
   return hipGetLastError();
 }
 

@@ -20,7 +20,8 @@ constexpr int kHist = 128;                         // histogram bins over n
 //   W   [f-1][kMaxCand]        weights of the full window per target
 //   var [kMaxUpsample]         their kriging variances
 //   G   [kMaxCand][kMaxCand]   C^{-1} of the full window (row-major)
-//   U   [kMaxUpsample][kMaxCand]  row 0: C^{-1} 1, row t: C^{-1} c0_t
+//   U   [kMaxUpsample][kMaxCand]  row 0: C^{-1} 1, row t: C^{-1} c0_t,
+//                              last row: C^{-1} s (the slice predictor)
 //   C0  [kMaxUpsample-1][kMaxCand] row t-1: c0_t of the full window
 // Systems that drop at most kMaxDrop candidates of the full window take
 // their weights from G and U (a k x k solve per system).
@@ -140,7 +141,7 @@ hipError_t launch_solve_mixed(const SolveArgs& a, int grid, hipStream_t s);
 // ---- launchers (kernels_points.hip) ----
 // Smallest neighbour count whose systems the weight cache serves by the
 // k x k solve (whole size classes of the solve kernels, at most kMaxDrop
-// dropped candidates); ncand when none (or with the slice predictor).
+// dropped candidates); ncand when none.
 int pattern_downdate_floor(const Geometry& g);
 // The full window's weights, inverse and solves, then its systems' estimates.
 hipError_t launch_pattern(const float* slices, const uint8_t* count, DevCounters* c,

@@ -290,12 +290,13 @@ def _downdate_floor(ncand, nb, max_drop=32):
     return ncand
 
 
+@pytest.mark.parametrize("drift", [None, "linear_z"], ids=["ok", "drift"])
 @pytest.mark.parametrize("case", [CASES[0], CASES[2]], ids=[CASES[0][0], CASES[2][0]])
-def test_pattern_cache_splits_exactly(case):
+def test_pattern_cache_splits_exactly(case, drift):
     """Systems below the cache's range are bit-identical to the batched
     launch; full-window systems, and those that drop at most 32 candidates
     (weights from the full window's inverse), match the FP64 batched solve to
-    float32 rounding."""
+    float32 rounding; with and without the slice predictor."""
     import torch
     import paper_2303_09523_amd as P
     name, n, ny, nx, f, r, model, nug, sill, rng_, masked, seed = case
@@ -303,16 +304,18 @@ def test_pattern_cache_splits_exactly(case):
     e = W.sobel_edges(s) if masked else None      # phantom edges only: full windows exist
     vario = (model, nug, sill, rng_)
     mp = min(4, 2 * (2 * r + 1) ** 2)
-    vb, wb, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", min_points=mp, refine_max=0)
+    kw = {"drift": drift} if drift else {}
+    vb, wb, _, _ = run_gpu(s, e, f, r, vario, precision="mixed_fp16", min_points=mp,
+                           refine_max=0, **kw)
     vp, wp, fp, sp = run_gpu(s, e, f, r, vario, precision="mixed_fp16", min_points=mp,
-                             algo="pattern", refine_max=0, flags=True)
-    v64, w64, _, _ = run_gpu(s, e, f, r, vario, precision="fp64", min_points=mp)
+                             algo="pattern", refine_max=0, flags=True, **kw)
+    v64, w64, _, _ = run_gpu(s, e, f, r, vario, precision="fp64", min_points=mp, **kw)
     plan = P.Plan(nx, ny, n, f, r, mp)
     _, count = plan.select(torch.from_numpy(e).cuda() if e is not None else None)
     plan.close()
     ncand = 2 * (2 * r + 1) ** 2
     cnt = (count.cpu().numpy() & 0x7f).reshape(n - 1, ny, nx)
-    full = cnt >= _downdate_floor(ncand, f + 1)
+    full = cnt >= _downdate_floor(ncand, f + 1 + (1 if drift else 0))
     print(f"full-window systems {(cnt == ncand).sum()}, from the inverse "
           f"{full.sum() - (cnt == ncand).sum()}, batched {(~full).sum()} of {full.size}",
           flush=True)
