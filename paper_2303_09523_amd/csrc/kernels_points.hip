@@ -94,26 +94,54 @@ __device__ bool chol_lds(double* A, int n) {
   return false;
 }
 
-// The factorisation of chol_lds by a whole workgroup: each step scales the
-// pivot column and then applies every element update of the trailing matrix
-// in one pass, so each element sees the same operations in the same order
-// and the factor is identical. Returns true (uniformly) on a non-positive
-// pivot.
+// The factorisation of chol_lds by a whole workgroup, two columns per step:
+// every thread reads the 2 x 2 pivot block, then each wave takes rows i of the
+// trailing matrix (its lanes the columns j <= i) and applies both rank-1
+// updates in turn, a_ij - l_i0 l_j0 - l_i1 l_j1 with l_i1 from the updated
+// a_i,p+1, reading columns p and p + 1 as they were; after a barrier the two
+// scaled columns are written. Each element sees the operations of two single
+// steps in their order, so the factor is that of chol_lds. Returns true
+// (uniformly) on a non-positive pivot.
 __device__ bool chol_block(double* A, int n) {
-  for (int k = 0; k < n; ++k) {
-    const double d = A[k * kPtLd + k];
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  int p = 0;
+  for (; p + 1 < n; p += 2) {
+    const double d0 = A[p * kPtLd + p];
+    if (!(d0 > 0.0)) return true;
+    const double is0 = 1.0 / sqrt(d0);
+    const double l10 = A[(p + 1) * kPtLd + p] * is0;
+    const double d1 = A[(p + 1) * kPtLd + p + 1] - l10 * l10;
+    if (!(d1 > 0.0)) return true;
+    const double is1 = 1.0 / sqrt(d1);
+    // trailing rows over waves, the row's columns over lanes
+    for (int i = p + 2 + (int)(threadIdx.x >> 6); i < n; i += nw) {
+      const double li0 = A[i * kPtLd + p] * is0;
+      const double li1 = (A[i * kPtLd + p + 1] - li0 * l10) * is1;
+      for (int j = p + 2 + lane; j <= i; j += 64) {
+        const double lj0 = A[j * kPtLd + p] * is0;
+        const double lj1 = (A[j * kPtLd + p + 1] - lj0 * l10) * is1;
+        A[i * kPtLd + j] = (A[i * kPtLd + j] - li0 * lj0) - li1 * lj1;
+      }
+    }
+    __syncthreads();   // every read of columns p, p + 1 and of the pivots is done
+    for (int i = p + 2 + (int)threadIdx.x; i < n; i += blockDim.x) {
+      const double li0 = A[i * kPtLd + p] * is0;
+      A[i * kPtLd + p] = li0;
+      A[i * kPtLd + p + 1] = (A[i * kPtLd + p + 1] - li0 * l10) * is1;
+    }
+    if (threadIdx.x == 0) {
+      A[p * kPtLd + p] = d0 * is0;               // L[p][p] = sqrt(d0)
+      A[(p + 1) * kPtLd + p] = l10;
+      A[(p + 1) * kPtLd + p + 1] = d1 * is1;     // L[p+1][p+1] = sqrt(d1)
+    }
+    __syncthreads();
+  }
+  if (p < n) {   // the last column of an odd n
+    const double d = A[p * kPtLd + p];
     if (!(d > 0.0)) return true;
     const double is = 1.0 / sqrt(d);
     __syncthreads();   // every thread has read the pivot
-    for (int i = k + 1 + (int)threadIdx.x; i < n; i += blockDim.x) A[i * kPtLd + k] *= is;
-    if (threadIdx.x == 0) A[k * kPtLd + k] = d * is;   // L[k][k] = sqrt(d)
-    __syncthreads();
-    // rows over waves, the row's columns over lanes
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int i = k + 1 + (int)(threadIdx.x >> 6); i < n; i += nw) {
-      const double lik = A[i * kPtLd + k];
-      for (int j = k + 1 + lane; j <= i; j += 64) A[i * kPtLd + j] -= lik * A[j * kPtLd + k];
-    }
+    if (threadIdx.x == 0) A[p * kPtLd + p] = d * is;
     __syncthreads();
   }
   return false;
