@@ -25,7 +25,8 @@ Prints ONE JSON line. Extra keys:
   accuracy          the headline result vs the oracle on that sample
   batched_variants  the other operating points (read-out only, FP64, FP32),
                     each with its accuracy on the same sample
-  next_rows         pattern_cache (full-window weight cache), marching_cubes and
+  next_rows         pattern_cache (full-window stencil and window-inverse
+                    solves), marching_cubes and
                     edge_postpass, below
   plain_fp32        the per-voxel comparison kernel (FP32 with its FP64-residual
                     refinement step, at the same per-voxel 1e-5 bar), on a slab
@@ -472,7 +473,7 @@ def main():
     ap.add_argument("--loso-only", action="store_true",
                     help="only the leave-one-slice-out timing (for profiling its kernels)")
     ap.add_argument("--pattern-only", action="store_true",
-                    help="only the full-window weight cache plan, profiled per phase")
+                    help="only the pattern-cache plan, profiled per phase")
     ap.add_argument("--mcubes-only", action="store_true",
                     help="only marching cubes on the reconstructed volume")
     ap.add_argument("--edge-only", action="store_true",
@@ -867,7 +868,7 @@ def main():
         "accuracy": acc,
         "plain_fp32": plain,
         "batched_variants": {k: v for k, v in others.items() if k not in NEXT_ROWS},
-        # the rows beyond the path: full-window weight cache, marching cubes and
+        # the rows beyond the path: pattern cache, marching cubes and
         # the paper's edge post-pass
         "next_rows": {k: others[k] for k in NEXT_ROWS if k in others},
         "loso": loso,
