@@ -253,7 +253,13 @@ def test_strict_mode_reports_failed_systems():
     plan.close()
 
 
-@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+# f = 14 puts the cache's inverse range at n >= 66 (drop counts up to 32, the
+# largest the k x k solves take); the masks leave systems across that range
+PATTERN_CASES = CASES + [
+    ("r3_f14_k32", 3, 30, 33, 14, 3, "exponential", 0.01, 1.0, 6.0, True, 14)]
+
+
+@pytest.mark.parametrize("case", PATTERN_CASES, ids=[c[0] for c in PATTERN_CASES])
 @pytest.mark.parametrize("precision", ["fp32", "mixed_fp16"])
 def test_pattern_cache_vs_oracle(case, precision, oracle_cache):
     """PATTERN_CACHE: full-window systems from the cached FP64 weights, the rest
@@ -277,6 +283,8 @@ def test_pattern_cache_vs_oracle(case, precision, oracle_cache):
     if precision == "fp32":
         assert nw <= NORMWISE_FP32
     assert st["bucket"] == np.bincount(npts.ravel(), minlength=128).tolist()
+    if name == "r3_f14_k32":
+        assert sum(st["bucket"][66:76]) > 0   # drop counts 23..32 present
 
 
 def _downdate_floor(ncand, nb, max_drop=32):
