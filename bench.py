@@ -760,9 +760,9 @@ def main():
             print(f"# precision study {name}: {ent}", file=sys.stderr, flush=True)
 
     # ---- the small and the edge-preserved workloads: batched, mixed, plain ----
-    configs = None
+    other_workloads = None
     if not args.no_extra:
-        configs = {}
+        other_workloads = {}
         for name in ("plain_8x64", "edge_32x256"):
             wx, sx, ex_, sampx = extra_inputs[name]
             stx = torch.from_numpy(sx).to(dev)
@@ -795,7 +795,7 @@ def main():
                               "n_fp64_resolved": sx_["n_fp64_fallback"],
                               "accuracy": _sample_accuracy(wx, sx, sampx, vx, varx)}
                 print(f"# {name} {label}: {med:.3f} ms", file=sys.stderr, flush=True)
-            configs[name] = ent
+            other_workloads[name] = ent
 
     # ---- variogram fit: 200 Adam steps on the leave-one-slice-out loss ----
     fit = None
@@ -874,7 +874,7 @@ def main():
         "loso": loso,
         "variogram_fit": fit,
         "precision_study": study,
-        "other_configs": configs,
+        "other_configs": other_workloads,
         "calibration": calib,
         "phases_ms_per_step": {k: round(v / args.steps, 4) for k, v in pstats["phase_ms"].items()},
         "solver_stats": dict({k: stats[k] for k in ("n_systems", "n_refined", "n_fp64_fallback",
